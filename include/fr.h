@@ -1,0 +1,240 @@
+/*
+ * fr.h -- exhaustive filtered top-K retrieval on AMD MI355X (gfx950).
+ *
+ * The operation is the paper's on-GPU hybrid retrieval (Sec. 5.3, "System
+ * Implementation", and the appendix "Optimizing System on GPU"): every query
+ * is checked against every document by a term predicate in conjunctive
+ * normal form (F-TBR), every matching document is scored by the inner
+ * product of its embedding with the query embedding (F-EBR), and the K best
+ * scores are returned (appendix, "Fast Top K Selection").  Queries are
+ * processed in batches that share one pass over the corpus (appendix,
+ * "Batch Inference"), and every byte of device memory is reserved when the
+ * index is created (appendix, "Memory Pre-Allocation").
+ *
+ * Conventions for every entry point:
+ *  - Return value: FR_OK (0) or a negative fr_status.  On error a
+ *    thread-local message is available from fr_last_error(); outputs are
+ *    unspecified and the index is unchanged, except FR_EDEVICE, which marks
+ *    the index as failed so that later calls return FR_EDEVICE at once.
+ *  - The caller owns every pointer it passes; the library never frees or
+ *    keeps them.  The library owns the corpus and its workspaces.
+ *  - Pointers are host memory unless FR_DEVICE_PTRS is set in `flags`; then
+ *    embeddings, ids, queries and outputs are device pointers on the
+ *    index's device.  Term lists, CNF batches and K values are always host
+ *    memory, because the host validates and compiles them.
+ *  - One call at a time per index, except fr_search calls that run on
+ *    different streams (at most `n_workspaces` in flight).
+ */
+#ifndef FR_H
+#define FR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fr_index fr_index;  /* opaque; owns all device memory */
+
+typedef enum {
+  FR_OK = 0,
+  FR_EINVAL = -1,        /* bad argument (sizes, term id >= vocab, K > k_max...) */
+  FR_ENOMEM = -2,        /* device or pinned allocation failed in fr_create */
+  FR_ECAPACITY = -3,     /* more live documents than `capacity` */
+  FR_EDUPID = -4,        /* inserting an id that is already live */
+  FR_ENOTFOUND = -5,     /* deleting an id that is not live */
+  FR_EUNSUPPORTED = -6,  /* configuration or input this build does not handle */
+  FR_EDEVICE = -7,       /* a HIP call failed; the index is no longer usable */
+  FR_EBUSY = -8          /* no free workspace and FR_NOWAIT was given */
+} fr_status;
+
+typedef enum {
+  FR_F32 = 0,            /* corpus scored in FP32 on the matrix cores */
+  FR_BF16 = 1,           /* BF16 corpus + BF16 query, FP32 accumulate, FP32 rescore */
+  FR_FP8_E4M3 = 2        /* OCP E4M3FN corpus with one FP32 scale per row and
+                            per query, FP32 accumulate, FP32 rescore */
+} fr_dtype;
+
+/* flags */
+#define FR_DEVICE_PTRS 1u  /* data pointers are device pointers (see above) */
+#define FR_NOWAIT      2u  /* fr_search: return FR_EBUSY instead of waiting for a workspace */
+
+typedef struct {
+  uint64_t capacity;       /* maximum live documents (slots); rounded up to 1024 */
+  uint32_t dim;            /* embedding dimension, 1..256 (padded to 64 inside) */
+  uint32_t vocab;          /* term ids are in [0, vocab), vocab <= 1<<20 */
+  uint32_t k_max;          /* largest K a query may ask for, 1..4096 */
+  uint32_t rescore_r;      /* BF16/FP8: most approximate candidates rescored in
+                              FP32 per query (R), k_max..4096; 0 -> 4096.
+                              Ignored for FR_F32 */
+  uint32_t rescore_min;    /* BF16/FP8: query q rescores
+                              R_q = min(rescore_r, max(rescore_min, 4*k[q]))
+                              candidates; 0 -> rescore_r (the same R for all) */
+  fr_dtype dtype;
+  uint32_t max_batch;      /* most queries per fr_search call (0 -> 1024) */
+  uint32_t max_clauses;    /* most clauses per batch (0 -> 8 per query) */
+  uint32_t max_literals;   /* most literals per batch (0 -> 32 per query) */
+  uint32_t n_workspaces;   /* fr_search calls that may be in flight (0 -> 1) */
+  uint32_t cand_cap;       /* candidate slots per query per pass (0 -> default) */
+  int device;              /* HIP device ordinal */
+} fr_config;
+
+/* A batch of CNF predicates in CSR-of-CSR form (host memory):
+ * query q has clauses [clause_off[q], clause_off[q+1]); clause c has
+ * literals terms[literal_off[c] .. literal_off[c+1]).  A document matches
+ * query q iff for every clause it holds at least one literal term.  A query
+ * with no clause matches every live document; an empty clause matches none.
+ * Duplicate literals are allowed.  (Sec. 5.3: each TBR query becomes a CNF;
+ * appendix "TBR": a clause is met when the document's values overlap it.) */
+typedef struct {
+  uint32_t n_queries;
+  const uint32_t* clause_off;   /* [n_queries + 1], clause_off[0] = 0 */
+  const uint32_t* literal_off;  /* [n_clauses + 1], literal_off[0] = 0 */
+  const uint32_t* terms;        /* [n_literals] */
+} fr_cnf_batch;
+
+/* Per-call statistics of the last completed fr_search (host memory). */
+typedef struct {
+  uint32_t n_queries;
+  uint32_t n_passes;        /* scan passes (1 unless a candidate buffer overflowed) */
+  uint64_t candidates;      /* candidates appended over all queries and passes */
+  uint64_t n_live;          /* live documents scanned */
+  uint64_t n_terms_batch;   /* distinct terms referenced by the batch */
+  double   alg_bytes;       /* algorithmic HBM bytes of the scan */
+  double   alg_flops;       /* 2 * dim * n_queries * n_slots_scanned */
+  float    ms_scan;         /* device time of the scan kernel(s) */
+  float    ms_total;        /* device time from first to last kernel */
+} fr_search_stats;
+
+/* Create an index on `cfg->device` and reserve all its device memory:
+ * corpus storage for `capacity` documents (embeddings in the chosen dtype,
+ * an FP32 master copy for the rescoring dtypes, per-term document bitmaps
+ * of vocab bits per document, ids, live bits) and `n_workspaces` search
+ * workspaces sized by max_batch / k_max / rescore_r (appendix, "Memory
+ * Pre-Allocation").  `out` receives the handle.  Errors: FR_EINVAL,
+ * FR_EUNSUPPORTED, FR_ENOMEM, FR_EDEVICE. */
+fr_status fr_create(const fr_config* cfg, fr_index** out);
+
+/* Release everything the index owns.  NULL is allowed.  Waits for work in
+ * flight on the index's streams. */
+fr_status fr_destroy(fr_index* ix);
+
+/* Replace the whole corpus by `n` documents.
+ * emb:      n x dim FP32, row-major (host, or device with FR_DEVICE_PTRS);
+ *           values must be finite.
+ * ids:      n external ids, unique, each < 0xFFFFFFFF.
+ * term_off: n + 1 offsets (host) into `terms` (host); the term list of doc
+ *           i is terms[term_off[i] .. term_off[i+1]), ids < vocab,
+ *           duplicates allowed.
+ * Documents occupy slots 0..n-1 in input order.  Synchronous.
+ * Errors: FR_EINVAL (shape, non-finite value, duplicate id, term >= vocab),
+ * FR_ECAPACITY (n > capacity), FR_EDEVICE. */
+fr_status fr_load_corpus(fr_index* ix, uint64_t n, const float* emb, const uint32_t* ids,
+                         const uint64_t* term_off, const uint32_t* terms, uint32_t flags);
+
+/* Delete `n_del` live ids, then insert `n_ins` new documents (same layout
+ * as fr_load_corpus, host memory), as one all-or-nothing update: the whole call is
+ * validated before any device work (unknown or repeated delete id ->
+ * FR_ENOTFOUND; inserting an id that stays live -> FR_EDUPID; too many
+ * live docs -> FR_ECAPACITY).  Freed slots are reused.  The update is
+ * ordered after every search already issued on the index and before every
+ * later one.  `out_epoch` (may be NULL) receives the new corpus epoch
+ * (incremented once per successful load or update).  Synchronous. */
+fr_status fr_update_docs(fr_index* ix, uint64_t n_del, const uint32_t* del_ids,
+                         uint64_t n_ins, const uint32_t* ins_ids, const float* ins_emb,
+                         const uint64_t* ins_term_off, const uint32_t* ins_terms,
+                         uint64_t* out_epoch);
+
+/* Filtered top-K for a batch of n_q queries in one pass over the corpus.
+ * queries:   n_q x dim FP32 row-major.
+ * cnf:       predicates (host, see fr_cnf_batch), cnf->n_queries == n_q.
+ * k:         n_q values (host), each 0..k_max.
+ * out_ids:   n_q x k_max; row q holds the ids of the best min(k[q],
+ *            n_match[q]) matches ordered by (score desc, id asc), then
+ *            0xFFFFFFFF.
+ * out_scores:n_q x k_max FP32 scores (the FP32 inner product; for BF16/FP8
+ *            the FP32 rescored value), then -INFINITY.
+ * out_count: n_q entries, min(k[q], n_match[q]).
+ * out_nmatch:n_q entries, live documents satisfying the predicate.
+ * stream:    NULL -> synchronous on the index's stream.  Otherwise a
+ *            hipStream_t; the call is enqueued and returns, and requires
+ *            FR_DEVICE_PTRS (inputs and outputs stay valid until the
+ *            stream passes the call).
+ * For BF16/FP8 indexes the approximate scores select the best min(R_q,
+ * n_match) candidates by (approximate score desc, id asc), which are
+ * rescored in FP32 and ordered by (FP32 score desc, id asc).
+ * Errors: FR_EINVAL, FR_EBUSY (FR_NOWAIT and no free workspace),
+ * FR_EUNSUPPORTED, FR_EDEVICE. */
+fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_cnf_batch* cnf,
+                    const uint32_t* k, uint32_t* out_ids, float* out_scores,
+                    uint32_t* out_count, uint64_t* out_nmatch, void* stream, uint32_t flags);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* fr_last_error(void);
+
+/* Statistics of the last synchronous fr_search (or of the last one whose
+ * stream has completed when fr_stats is called).  */
+fr_status fr_stats(fr_index* ix, fr_search_stats* out);
+
+/* Device times of the most recent fr_search calls (at most `max`, oldest
+ * first, at most 64 remembered): scan_ms[i] is the first scan pass,
+ * total_ms[i] the whole call from the first scan to the last kernel (both
+ * measured with HIP events on the call's stream).  `n` receives how many
+ * were written; waits for those calls to finish.  Either array may be
+ * NULL. */
+fr_status fr_timings(fr_index* ix, uint32_t max, float* scan_ms, float* total_ms, uint32_t* n);
+
+/* Current number of live documents, corpus epoch and slots in use (the
+ * highest occupied slot + 1).  Any output may be NULL. */
+fr_status fr_info(fr_index* ix, uint64_t* n_live, uint64_t* epoch, uint64_t* n_slots);
+
+/* ---- testing and tuning entry points ---------------------------------- */
+
+/* Predicate masks only (step 2 of the hot path, Sec. 5.3): out_bits (host)
+ * receives n_q rows of ceil(n_slots/64) 64-bit words; bit s of row q is set
+ * iff slot s is live and satisfies query q.  Slot s of fr_load_corpus is
+ * input row s; fr_debug_slots maps slots to ids after updates.
+ * Synchronous. */
+fr_status fr_debug_masks(fr_index* ix, const fr_cnf_batch* cnf, uint64_t* out_bits,
+                         uint64_t n_words_per_query);
+
+/* Stored element codes of slots [slot0, slot0+n): out_codes receives
+ * n x dpad elements row-major in the index dtype (FP32 values, BF16 bits as
+ * uint16, or E4M3FN codes as uint8; dpad = dim rounded up to 64, padding is
+ * zero) and, if not NULL, out_scales the n FP8 row scales (1.0 for other
+ * dtypes).  Pins the device quantizers.  Synchronous. */
+fr_status fr_debug_rows(fr_index* ix, uint64_t slot0, uint64_t n, void* out_codes,
+                        float* out_scales);
+
+/* Slot -> id table (host, n entries; 0xFFFFFFFF for a free slot). */
+fr_status fr_debug_slots(fr_index* ix, uint32_t* out_ids, uint64_t n);
+
+/* First-pass candidates of the last synchronous fr_search (BF16/FP8): for
+ * each query up to rescore_r ids and their approximate scores, ordered by
+ * (approximate score desc, id asc); `count` receives how many.  Host
+ * outputs of n_q x rescore_r. */
+fr_status fr_debug_candidates(fr_index* ix, uint32_t n_q, uint32_t* out_ids,
+                              float* out_scores, uint32_t* out_count);
+
+/* Scan tiling: `query_blocks` blocks of 32 queries per wavefront (1, 2 or
+ * 4) and `waves` wavefronts per workgroup (4 or 8), so one pass over a
+ * 1024-document group serves 32*query_blocks*waves queries; and
+ * `groups_per_item` groups per work item.  Zeros restore the per-batch
+ * defaults.  FR_EUNSUPPORTED if this build has no such scan kernel for the
+ * index's dtype and dimension.  Used by the autotuner and by tests. */
+fr_status fr_set_tiling(fr_index* ix, uint32_t query_blocks, uint32_t waves,
+                        uint32_t groups_per_item);
+
+/* Time every scan tiling this build has for the index's dtype and
+ * dimension on the given batch (host pointers; each candidate runs three
+ * searches, outputs are scratch) and keep the fastest.  The out_* pointers
+ * (may be NULL) receive the choice (0 = per-batch default for the groups). */
+fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr_cnf_batch* cnf,
+                      const uint32_t* k, uint32_t flags, uint32_t* out_query_blocks,
+                      uint32_t* out_waves, uint32_t* out_groups);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FR_H */

@@ -1,0 +1,231 @@
+// Internal declarations shared by the host runtime (fr_runtime.cpp) and the
+// HIP kernels (fr_kernels.hip).  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fr {
+
+constexpr int kTile = 32;            // documents per matrix-core tile
+constexpr int kGroup = 1024;         // documents per predicate group
+constexpr int kWords = kGroup / 64;  // 64-bit mask words per group
+constexpr int kNBF = 256;            // fine histogram buckets per query
+constexpr int kNBC = 16;             // coarse buckets (16 fine each)
+constexpr int kHist = kNBC + kNBF;   // u32 counters per query histogram
+constexpr int kXcds = 8;             // work queues (one per XCD)
+constexpr int kSelCap = 8192;        // candidates sorted in LDS by the select kernel
+constexpr int kMaxR = 4096;          // largest K / R handled by select and rescore
+constexpr uint32_t kKeyNegInf = 0x007FFFFFu;  // order key of -inf
+constexpr uint32_t kKeyPosInf = 0xFF800000u;  // order key of +inf
+
+enum Dtype : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+
+inline int elem_bytes(int dt) { return dt == kF32 ? 4 : dt == kBF16 ? 2 : 1; }
+// Bytes of one 32-row tile: rows are split into two halves of dpad/2
+// elements (one per 32-lane half of a wavefront) stored as 16-byte chunks in
+// [chunk][lane][16 B] order, so a wavefront loads a chunk as one contiguous
+// kilobyte.
+inline size_t tile_bytes(int dt, int dpad) { return (size_t)kTile * dpad * elem_bytes(dt); }
+
+// ---------------------------------------------------------------- kernels
+struct TileRowsArgs {
+  const float* rows;       // n x dim FP32 row-major (device)
+  uint64_t n;
+  uint32_t dim, dpad, dt;
+  const uint32_t* slots;   // destination slot of each row, or null -> slot_base + i
+  uint64_t slot_base;
+  uint8_t* tiles;          // tiled storage of the destination
+  float* scale;            // FP8: per-row scale out (indexed by slot); may be null otherwise
+  float* master;           // optional FP32 row copy [slot][dpad]
+  float* norm;             // optional per-row L2 norm out (indexed by i)
+  uint32_t* norm_max;      // optional running max of norms (float bits)
+  const uint32_t* n_dev;   // optional device row count (min with n)
+};
+
+struct TermArgs {
+  const uint64_t* off;     // n + 1 offsets into terms
+  const uint32_t* terms;
+  const uint32_t* slots;   // slot of each row, or null -> slot_base + i
+  uint64_t slot_base;
+  uint64_t n;
+  uint64_t* bits;          // [groups][vocab][16]
+  uint32_t vocab;
+  int set;                 // 1: set bits, 0: clear bits
+};
+
+struct LiveArgs {
+  const uint32_t* slots;   // or null -> slot_base + i
+  uint64_t slot_base;
+  uint64_t n;
+  const uint32_t* ids;     // id per row (set) or null (clear)
+  uint32_t* slot_ids;
+  uint64_t* live;
+  int set;
+};
+
+struct PrepArgs {
+  uint32_t max_q;          // grid size (queries the workspace can hold)
+  const uint32_t* n_dev;   // device: queries in this batch
+  const uint32_t* k;       // requested K per query
+  uint32_t* kp;            // first-pass selection size per query (out)
+  uint32_t dt;
+  uint32_t rescore_r, rescore_min;
+  const float* qnorm;      // per-query norm
+  const uint32_t* norm_max;
+  uint32_t* tau;
+  uint32_t* cnt;
+  uint32_t* smax;
+  uint32_t* hist;
+  float* hlo;
+  float* hinvw;
+  unsigned long long* nmatch;
+  uint32_t* qlist;
+  uint32_t* n_list;        // device: first-pass list length (= n_q)
+  uint32_t* n_list2;       // device: rerun list length (zeroed)
+  uint32_t* work;          // kXcds counters (zeroed)
+  uint32_t* ovf;           // per-query overflow flag
+  // CNF of the batch and its per-query literal table (out): up to 16 term
+  // ids per query, and an info word: bits 0-4 literal count (<= 16), 8-23
+  // first-literal-of-clause flags, 24 an empty clause, 25 more than 16
+  // literals (evaluated from the CSR arrays instead), 26 at least one clause.
+  const uint32_t* clause_off;
+  const uint32_t* literal_off;
+  const uint32_t* terms;
+  uint32_t* lit;
+  uint32_t* linfo;
+};
+
+// Second pass for queries whose candidate buffer overflowed: keep their
+// (safe, tightened) threshold, narrow the histogram range to [tau, max seen]
+// and clear their counters.
+struct RerunArgs {
+  uint32_t max_q;
+  const uint32_t* n_dev;
+  uint32_t* ovf;
+  uint32_t* qlist2;
+  uint32_t* n_list2;
+  uint32_t* tau;
+  uint32_t* cnt;
+  uint32_t* smax;
+  uint32_t* hist;
+  float* hlo;
+  float* hinvw;
+  uint32_t* work;
+};
+
+struct ScanArgs {
+  const uint8_t* tiles;
+  const float* xscale;     // FP8 row scales or null
+  const uint32_t* slot_ids;
+  const uint64_t* live;
+  const uint64_t* bits;
+  uint32_t vocab;
+  uint32_t n_groups;
+  const uint8_t* qtiles;
+  const float* qscale;     // FP8 query scales or null
+  const uint32_t* qlist;
+  const uint32_t* n_list;  // device
+  const uint32_t* kp;
+  uint32_t* tau;
+  uint32_t* cnt;
+  uint32_t* smax;
+  uint32_t* hist;
+  const float* hlo;
+  const float* hinvw;
+  unsigned long long* cand_key;
+  uint32_t* cand_slot;
+  uint32_t cap;
+  unsigned long long* nmatch;
+  uint32_t* work;
+  uint32_t gpi;            // groups per work item
+  uint32_t count_matches;
+  const uint32_t* clause_off;
+  const uint32_t* literal_off;
+  const uint32_t* terms;
+  const uint32_t* lit;     // per-query literal table (see PrepArgs)
+  const uint32_t* linfo;
+};
+
+struct SelectArgs {
+  const uint32_t* qlist;
+  const uint32_t* n_list;  // device
+  uint32_t max_list;       // grid size
+  int final_pass;          // overflow here is final: mark the query failed
+  const uint32_t* kp;
+  const uint32_t* tau;
+  const uint32_t* cnt;
+  const unsigned long long* cand_key;
+  const uint32_t* cand_slot;
+  uint32_t cap;
+  unsigned long long* sel_key;   // [q][rmax]
+  uint32_t* sel_slot;
+  uint32_t* sel_cnt;
+  uint32_t rmax;
+  uint32_t* ovf;
+  // direct output (FP32 path)
+  int write_out;
+  const uint32_t* k;
+  uint32_t k_max;
+  uint32_t* out_ids;
+  float* out_scores;
+  uint32_t* out_count;
+  const unsigned long long* nmatch;
+  unsigned long long* out_nmatch;
+};
+
+struct RescoreArgs {
+  uint32_t max_q;
+  const uint32_t* n_dev;
+  const uint32_t* ovf;
+  const float* master;     // [slot][dpad]
+  const float* qrows;      // [q][dpad]
+  uint32_t dpad;
+  const unsigned long long* sel_key;
+  const uint32_t* sel_slot;
+  const uint32_t* sel_cnt;
+  uint32_t rmax;
+  const uint32_t* k;
+  uint32_t k_max;
+  uint32_t* out_ids;
+  float* out_scores;
+  uint32_t* out_count;
+  const unsigned long long* nmatch;
+  unsigned long long* out_nmatch;
+};
+
+struct MaskArgs {
+  const uint64_t* live;
+  const uint64_t* bits;
+  uint32_t vocab;
+  uint32_t n_q;
+  uint64_t n_words;        // words per query row of the output
+  const uint32_t* clause_off;
+  const uint32_t* literal_off;
+  const uint32_t* terms;
+  unsigned long long* out;
+};
+
+// Launchers (fr_kernels.hip).  Each returns the HIP error of the launch.
+hipError_t launch_tile_rows(const TileRowsArgs& a, hipStream_t s);
+hipError_t launch_terms(const TermArgs& a, hipStream_t s);
+hipError_t launch_live(const LiveArgs& a, hipStream_t s);
+hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
+hipError_t launch_rerun(const RerunArgs& a, hipStream_t s);
+hipError_t launch_zero_work(uint32_t* work, hipStream_t s);
+hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int n_wg,
+                       hipStream_t s);
+hipError_t launch_select(const SelectArgs& a, hipStream_t s);
+hipError_t launch_rescore(const RescoreArgs& a, hipStream_t s);
+hipError_t launch_masks(const MaskArgs& a, uint64_t n_words_total, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+// Clear every term bit of the given slots (documents being deleted).
+hipError_t launch_clear_slot_terms(const uint32_t* slots, uint64_t n, uint64_t* bits,
+                                   uint32_t vocab, hipStream_t s);
+// flag |= 1 if any of x[0..n) is not finite.
+hipError_t launch_check_finite(const float* x, uint64_t n, uint32_t* flag, hipStream_t s);
+// Scan variants: query blocks of 32 per wavefront x wavefronts per workgroup.
+bool scan_supported(int dt, int dpad, int qb, int nw);
+
+}  // namespace fr

@@ -1,0 +1,1210 @@
+// Host runtime of the filtered top-K retrieval library: the C ABI of
+// include/fr.h, input validation, the slot store (id map, free slots,
+// epochs), pre-allocated workspaces, and the launch sequence of a search.
+//
+// Every device allocation happens in fr_create (appendix "Memory
+// Pre-Allocation"); later calls only validate, copy and launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <queue>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "fr.h"
+#include "fr_internal.h"
+
+using namespace fr;
+
+namespace {
+
+thread_local std::string g_err;
+
+fr_status fail(fr_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+#define FR_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      ix->failed = true;                                                              \
+      return fail(FR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    }                                                                                 \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t count, std::vector<void*>& owned) {
+  void* v = nullptr;
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  hipError_t e = hipMalloc(&v, bytes);
+  if (e == hipSuccess) owned.push_back(v);
+  *p = (T*)v;
+  return e;
+}
+
+template <class T>
+hipError_t halloc(T** p, size_t count, std::vector<void*>& owned) {
+  void* v = nullptr;
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  hipError_t e = hipHostMalloc(&v, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) owned.push_back(v);
+  *p = (T*)v;
+  return e;
+}
+
+uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct Workspace {
+  // device
+  float* qrow = nullptr;
+  uint8_t* qtiles = nullptr;
+  float* qscale = nullptr;
+  float* qnorm = nullptr;
+  uint32_t* clause_off = nullptr;
+  uint32_t* literal_off = nullptr;
+  uint32_t* terms = nullptr;
+  uint32_t* k = nullptr;
+  uint32_t* kp = nullptr;
+  uint32_t* tau = nullptr;
+  uint32_t* cnt = nullptr;
+  uint32_t* smax = nullptr;
+  uint32_t* hist = nullptr;
+  uint32_t* qlist = nullptr;
+  uint32_t* qlist2 = nullptr;
+  uint32_t* ovf = nullptr;
+  uint32_t* sel_cnt = nullptr;
+  uint32_t* lit = nullptr;
+  uint32_t* linfo = nullptr;
+  uint32_t* desc = nullptr;  // [0] n_q, [1] n_list, [2] n_list2
+  uint32_t* work = nullptr;
+  float* hlo = nullptr;
+  float* hinvw = nullptr;
+  unsigned long long* nmatch = nullptr;
+  unsigned long long* cand_key = nullptr;
+  uint32_t* cand_slot = nullptr;
+  unsigned long long* sel_key = nullptr;
+  uint32_t* sel_slot = nullptr;
+  uint32_t* out_ids = nullptr;
+  float* out_scores = nullptr;
+  uint32_t* out_count = nullptr;
+  unsigned long long* out_nmatch = nullptr;
+  // pinned host staging
+  float* h_q = nullptr;
+  uint32_t* h_co = nullptr;
+  uint32_t* h_lo = nullptr;
+  uint32_t* h_terms = nullptr;
+  uint32_t* h_k = nullptr;
+  uint32_t* h_desc = nullptr;
+  uint32_t* h_ids = nullptr;
+  float* h_scores = nullptr;
+  uint32_t* h_count = nullptr;
+  unsigned long long* h_nmatch = nullptr;
+  uint32_t* h_cnt = nullptr;
+  uint32_t* h_selcnt = nullptr;
+  uint32_t* h_desc_out = nullptr;  // device descriptor after the call ([2] = rerun list)
+  hipEvent_t done = nullptr, e_scan0 = nullptr, e_scan1 = nullptr, e_end = nullptr;
+  // timing ring: scan start / scan end / end of the search, per recent call
+  static constexpr int kRing = 64;
+  hipEvent_t r0[kRing] = {}, r1[kRing] = {}, r2[kRing] = {};
+  uint64_t n_calls = 0;
+  bool in_flight = false;
+  uint32_t last_nq = 0;
+  double last_alg_bytes = 0, last_alg_flops = 0;
+  uint64_t last_terms = 0, last_live = 0;
+};
+
+struct fr_index {
+  fr_config cfg{};
+  int dt = 0;
+  uint32_t dim = 0, dpad = 0;
+  uint64_t cap = 0;        // slots, multiple of kGroup
+  uint32_t rmax = 0;       // per-query selection buffer (max of k_max and R)
+  uint32_t r = 0, r_min = 0;
+  uint32_t cand_cap = 0;
+  uint32_t qmax = 0, cmax = 0, lmax = 0;
+  int n_cu = 0, n_wg = 0;
+  int qb = 0, nw = 0, gpi = 0;   // 0: chosen per batch
+  hipStream_t stream = nullptr;
+  std::vector<void*> dev_owned, host_owned;
+  // corpus
+  uint8_t* tiles = nullptr;
+  float* xscale = nullptr;
+  float* master = nullptr;
+  uint32_t* slot_ids = nullptr;
+  uint64_t* live = nullptr;
+  uint64_t* bits = nullptr;
+  uint32_t* norm_max = nullptr;
+  uint32_t* d_flag = nullptr;
+  // load / update staging
+  uint64_t stage_rows = 0, stage_terms = 0;
+  float* d_rows = nullptr;
+  uint64_t* d_off = nullptr;
+  uint32_t* d_tl = nullptr;
+  uint32_t* d_ids = nullptr;
+  uint32_t* d_slots = nullptr;
+  uint32_t* h_flag = nullptr;
+  // host mirror of the slot store
+  std::unordered_map<uint32_t, uint32_t> id2slot;
+  std::vector<uint32_t> slot_id;
+  std::priority_queue<uint32_t, std::vector<uint32_t>, std::greater<uint32_t>> free_slots;
+  uint64_t hwm = 0, n_live = 0, epoch = 0;
+  std::vector<Workspace> ws;
+  size_t next_ws = 0;
+  bool failed = false;
+  fr_search_stats last{};
+  bool have_last = false;
+  size_t last_ws = 0;
+  std::vector<std::pair<uint32_t, uint32_t>> history;  // (workspace, ring slot) per call
+  std::mutex mu;
+};
+
+namespace {
+
+fr_status wait_all(fr_index* ix) {
+  for (auto& w : ix->ws) {
+    if (w.in_flight) {
+      FR_HIP(hipEventSynchronize(w.done));
+      w.in_flight = false;
+    }
+  }
+  FR_HIP(hipStreamSynchronize(ix->stream));
+  return FR_OK;
+}
+
+fr_status check_terms(const fr_index* ix, uint64_t n, const uint64_t* off, const uint32_t* terms) {
+  if (n && (!off || (off[n] > off[0] && !terms)))
+    return fail(FR_EINVAL, "term_off / terms missing");
+  for (uint64_t i = 0; i < n; ++i)
+    if (off[i + 1] < off[i]) return fail(FR_EINVAL, "term_off must be non-decreasing");
+  for (uint64_t j = n ? off[0] : 0; j < (n ? off[n] : 0); ++j)
+    if (terms[j] >= ix->cfg.vocab)
+      return fail(FR_EINVAL, "term id " + std::to_string(terms[j]) + " >= vocab");
+  return FR_OK;
+}
+
+// Finiteness of host rows, or of device rows via a kernel.
+fr_status check_rows(fr_index* ix, const float* emb, uint64_t n, bool dev) {
+  const uint64_t cnt = n * ix->dim;
+  if (!cnt) return FR_OK;
+  if (!emb) return fail(FR_EINVAL, "embeddings missing");
+  if (!dev) {
+    for (uint64_t i = 0; i < cnt; ++i)
+      if (!std::isfinite(emb[i])) return fail(FR_EINVAL, "non-finite embedding value");
+    return FR_OK;
+  }
+  FR_HIP(launch_fill_u32(ix->d_flag, 0u, 1, ix->stream));
+  FR_HIP(launch_check_finite(emb, cnt, ix->d_flag, ix->stream));
+  FR_HIP(hipMemcpyAsync(ix->h_flag, ix->d_flag, 4, hipMemcpyDeviceToHost, ix->stream));
+  FR_HIP(hipStreamSynchronize(ix->stream));
+  if (*ix->h_flag) return fail(FR_EINVAL, "non-finite embedding value");
+  return FR_OK;
+}
+
+// Write rows [0, n) into slots (slots == null -> slot_base + i), with
+// their term lists and ids.  Chunked through the pre-allocated staging.
+fr_status write_docs(fr_index* ix, uint64_t n, const float* emb, const uint32_t* ids,
+                     const uint64_t* off, const uint32_t* terms, const uint32_t* slots,
+                     uint64_t slot_base, bool dev) {
+  uint64_t r0 = 0;
+  while (r0 < n) {
+    uint64_t r1 = std::min(n, r0 + ix->stage_rows);
+    while (r1 > r0 + 1 && off[r1] - off[r0] > ix->stage_terms) r1 = r0 + (r1 - r0) / 2;
+    if (off[r1] - off[r0] > ix->stage_terms)
+      return fail(FR_EUNSUPPORTED, "a document has more terms than the staging buffer");
+    const uint64_t m = r1 - r0;
+    const float* rows = emb + r0 * ix->dim;
+    if (!dev) {
+      FR_HIP(hipMemcpyAsync(ix->d_rows, rows, m * ix->dim * sizeof(float), hipMemcpyHostToDevice,
+                            ix->stream));
+      rows = ix->d_rows;
+      FR_HIP(hipMemcpyAsync(ix->d_ids, ids + r0, m * 4, hipMemcpyHostToDevice, ix->stream));
+    } else {
+      FR_HIP(hipMemcpyAsync(ix->d_ids, ids + r0, m * 4, hipMemcpyDeviceToDevice, ix->stream));
+    }
+    std::vector<uint64_t> loc(m + 1);
+    for (uint64_t i = 0; i <= m; ++i) loc[i] = off[r0 + i] - off[r0];
+    FR_HIP(hipMemcpyAsync(ix->d_off, loc.data(), (m + 1) * 8, hipMemcpyHostToDevice, ix->stream));
+    if (loc[m])
+      FR_HIP(hipMemcpyAsync(ix->d_tl, terms + off[r0], loc[m] * 4, hipMemcpyHostToDevice,
+                            ix->stream));
+    if (slots)
+      FR_HIP(hipMemcpyAsync(ix->d_slots, slots + r0, m * 4, hipMemcpyHostToDevice, ix->stream));
+    TileRowsArgs ta{};
+    ta.rows = rows;
+    ta.n = m;
+    ta.dim = ix->dim;
+    ta.dpad = ix->dpad;
+    ta.dt = ix->dt;
+    ta.slots = slots ? ix->d_slots : nullptr;
+    ta.slot_base = slot_base + r0;
+    ta.tiles = ix->tiles;
+    ta.scale = ix->xscale;
+    ta.master = ix->master;
+    ta.norm_max = ix->norm_max;
+    FR_HIP(launch_tile_rows(ta, ix->stream));
+    TermArgs tm{};
+    tm.off = ix->d_off;
+    tm.terms = ix->d_tl;
+    tm.slots = ta.slots;
+    tm.slot_base = ta.slot_base;
+    tm.n = m;
+    tm.bits = ix->bits;
+    tm.vocab = ix->cfg.vocab;
+    tm.set = 1;
+    FR_HIP(launch_terms(tm, ix->stream));
+    LiveArgs la{};
+    la.slots = ta.slots;
+    la.slot_base = ta.slot_base;
+    la.n = m;
+    la.ids = ix->d_ids;
+    la.slot_ids = ix->slot_ids;
+    la.live = ix->live;
+    la.set = 1;
+    FR_HIP(launch_live(la, ix->stream));
+    // the staging buffers are reused by the next chunk
+    FR_HIP(hipStreamSynchronize(ix->stream));
+    r0 = r1;
+  }
+  return FR_OK;
+}
+
+// Scan tiling for a batch: query blocks of 32 per wavefront (qb) and
+// wavefronts per workgroup (nw), so qb*nw*32 queries share one pass over a
+// group.  Default: the largest such tile that the batch fills (rounded up to
+// 128 queries), preferring eight wavefronts (two per SIMD).
+void pick_tiling(const fr_index* ix, uint32_t n_q, int* qb, int* nw) {
+  if (ix->qb && ix->nw) {
+    *qb = ix->qb;
+    *nw = ix->nw;
+    return;
+  }
+  const uint32_t want = round_up(std::max<uint32_t>(n_q, 1), 128);
+  int bq = 1, bw = 4;
+  uint32_t best = 0;
+  for (int w : {4, 8})
+    for (int c : {1, 2, 4}) {
+      if (!scan_supported(ix->dt, ix->dpad, c, w)) continue;
+      const uint32_t qt = 32u * c * w;
+      if (qt > want && qt > 128) continue;
+      if (qt > best || (qt == best && w > bw)) {
+        best = qt;
+        bq = c;
+        bw = w;
+      }
+    }
+  *qb = bq;
+  *nw = bw;
+}
+
+// Groups per work item: about two items per workgroup, so that most groups'
+// predicate masks are computed under the previous group's matrix work.
+int pick_gpi(const fr_index* ix, uint32_t n_q, int qt, uint32_t n_groups) {
+  if (ix->gpi) return ix->gpi;
+  const uint64_t qtiles = (n_q + qt - 1) / qt;
+  const uint64_t g = (uint64_t)n_groups * qtiles / (2ull * ix->n_wg);
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 16));
+}
+
+fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_q,
+                         uint32_t* o_ids, float* o_scores, uint32_t* o_count,
+                         unsigned long long* o_nmatch) {
+  int qb = 1, nw = 4;
+  pick_tiling(ix, n_q, &qb, &nw);
+  const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
+  TileRowsArgs ta{};
+  ta.rows = w.qrow;
+  ta.n = ix->qmax;
+  ta.n_dev = w.desc;
+  ta.dim = ix->dpad;
+  ta.dpad = ix->dpad;
+  ta.dt = ix->dt;
+  ta.tiles = w.qtiles;
+  ta.scale = w.qscale;
+  ta.norm = w.qnorm;
+  FR_HIP(launch_tile_rows(ta, s));
+
+  PrepArgs pa{};
+  pa.max_q = ix->qmax;
+  pa.n_dev = w.desc;
+  pa.k = w.k;
+  pa.kp = w.kp;
+  pa.dt = ix->dt;
+  pa.rescore_r = ix->r;
+  pa.rescore_min = ix->r_min;
+  pa.qnorm = w.qnorm;
+  pa.norm_max = ix->norm_max;
+  pa.tau = w.tau;
+  pa.cnt = w.cnt;
+  pa.smax = w.smax;
+  pa.hist = w.hist;
+  pa.hlo = w.hlo;
+  pa.hinvw = w.hinvw;
+  pa.nmatch = w.nmatch;
+  pa.qlist = w.qlist;
+  pa.n_list = w.desc + 1;
+  pa.n_list2 = w.desc + 2;
+  pa.work = w.work;
+  pa.ovf = w.ovf;
+  pa.clause_off = w.clause_off;
+  pa.literal_off = w.literal_off;
+  pa.terms = w.terms;
+  pa.lit = w.lit;
+  pa.linfo = w.linfo;
+  FR_HIP(launch_prep(pa, s));
+
+  ScanArgs sa{};
+  sa.tiles = ix->tiles;
+  sa.xscale = ix->xscale;
+  sa.slot_ids = ix->slot_ids;
+  sa.live = ix->live;
+  sa.bits = ix->bits;
+  sa.vocab = ix->cfg.vocab;
+  sa.n_groups = n_groups;
+  sa.qtiles = w.qtiles;
+  sa.qscale = w.qscale;
+  sa.qlist = w.qlist;
+  sa.n_list = w.desc + 1;
+  sa.kp = w.kp;
+  sa.tau = w.tau;
+  sa.cnt = w.cnt;
+  sa.smax = w.smax;
+  sa.hist = w.hist;
+  sa.hlo = w.hlo;
+  sa.hinvw = w.hinvw;
+  sa.cand_key = w.cand_key;
+  sa.cand_slot = w.cand_slot;
+  sa.cap = ix->cand_cap;
+  sa.nmatch = w.nmatch;
+  sa.work = w.work;
+  sa.gpi = (uint32_t)pick_gpi(ix, n_q, 32 * qb * nw, n_groups);
+  sa.count_matches = 1;
+  sa.clause_off = w.clause_off;
+  sa.literal_off = w.literal_off;
+  sa.terms = w.terms;
+  const int slot = (int)(w.n_calls % Workspace::kRing);
+  w.e_scan0 = w.r0[slot];
+  w.e_scan1 = w.r1[slot];
+  w.e_end = w.r2[slot];
+  w.n_calls += 1;
+  ix->history.emplace_back((uint32_t)(&w - ix->ws.data()), (uint32_t)slot);
+  if (ix->history.size() > (size_t)Workspace::kRing)
+    ix->history.erase(ix->history.begin(), ix->history.begin() + (ix->history.size() - Workspace::kRing));
+  FR_HIP(hipEventRecord(w.e_scan0, s));
+  FR_HIP(launch_scan(sa, ix->dt, ix->dpad, qb, nw, ix->n_wg, s));
+  FR_HIP(hipEventRecord(w.e_scan1, s));
+
+  SelectArgs se{};
+  se.qlist = w.qlist;
+  se.n_list = w.desc + 1;
+  se.max_list = ix->qmax;
+  se.final_pass = 0;
+  se.kp = w.kp;
+  se.tau = w.tau;
+  se.cnt = w.cnt;
+  se.cand_key = w.cand_key;
+  se.cand_slot = w.cand_slot;
+  se.cap = ix->cand_cap;
+  se.sel_key = w.sel_key;
+  se.sel_slot = w.sel_slot;
+  se.sel_cnt = w.sel_cnt;
+  se.rmax = ix->rmax;
+  se.ovf = w.ovf;
+  se.write_out = ix->dt == kF32;
+  se.k = w.k;
+  se.k_max = ix->cfg.k_max;
+  se.out_ids = o_ids;
+  se.out_scores = o_scores;
+  se.out_count = o_count;
+  se.nmatch = w.nmatch;
+  se.out_nmatch = o_nmatch;
+  FR_HIP(launch_select(se, s));
+
+  // second pass for overflowed queries (an empty list when none did)
+  RerunArgs ra{};
+  ra.max_q = ix->qmax;
+  ra.n_dev = w.desc;
+  ra.ovf = w.ovf;
+  ra.qlist2 = w.qlist2;
+  ra.n_list2 = w.desc + 2;
+  ra.tau = w.tau;
+  ra.cnt = w.cnt;
+  ra.smax = w.smax;
+  ra.hist = w.hist;
+  ra.hlo = w.hlo;
+  ra.hinvw = w.hinvw;
+  ra.work = w.work;
+  FR_HIP(launch_rerun(ra, s));
+  ScanArgs sb = sa;
+  sb.qlist = w.qlist2;
+  sb.n_list = w.desc + 2;
+  sb.count_matches = 0;
+  FR_HIP(launch_scan(sb, ix->dt, ix->dpad, qb, nw, ix->n_wg, s));
+  SelectArgs sf = se;
+  sf.qlist = w.qlist2;
+  sf.n_list = w.desc + 2;
+  sf.final_pass = 1;
+  FR_HIP(launch_select(sf, s));
+
+  if (ix->dt != kF32) {
+    RescoreArgs rs{};
+    rs.max_q = ix->qmax;
+    rs.n_dev = w.desc;
+    rs.ovf = w.ovf;
+    rs.master = ix->master;
+    rs.qrows = w.qrow;
+    rs.dpad = ix->dpad;
+    rs.sel_key = w.sel_key;
+    rs.sel_slot = w.sel_slot;
+    rs.sel_cnt = w.sel_cnt;
+    rs.rmax = ix->rmax;
+    rs.k = w.k;
+    rs.k_max = ix->cfg.k_max;
+    rs.out_ids = o_ids;
+    rs.out_scores = o_scores;
+    rs.out_count = o_count;
+    rs.nmatch = w.nmatch;
+    rs.out_nmatch = o_nmatch;
+    FR_HIP(launch_rescore(rs, s));
+  }
+  FR_HIP(hipEventRecord(w.e_end, s));
+  return FR_OK;
+}
+
+fr_status validate_cnf(const fr_index* ix, uint32_t n_q, const fr_cnf_batch* cnf, uint32_t* n_c,
+                       uint32_t* n_l) {
+  if (!cnf) return fail(FR_EINVAL, "cnf batch missing");
+  if (cnf->n_queries != n_q) return fail(FR_EINVAL, "cnf->n_queries != n_q");
+  if (!cnf->clause_off) return fail(FR_EINVAL, "clause_off missing");
+  if (cnf->clause_off[0] != 0) return fail(FR_EINVAL, "clause_off[0] must be 0");
+  for (uint32_t q = 0; q < n_q; ++q)
+    if (cnf->clause_off[q + 1] < cnf->clause_off[q])
+      return fail(FR_EINVAL, "clause_off must be non-decreasing");
+  const uint32_t c = cnf->clause_off[n_q];
+  if (c > ix->cmax) return fail(FR_EINVAL, "more clauses than max_clauses");
+  if (c && !cnf->literal_off) return fail(FR_EINVAL, "literal_off missing");
+  if (c && cnf->literal_off[0] != 0) return fail(FR_EINVAL, "literal_off[0] must be 0");
+  for (uint32_t i = 0; i < c; ++i)
+    if (cnf->literal_off[i + 1] < cnf->literal_off[i])
+      return fail(FR_EINVAL, "literal_off must be non-decreasing");
+  const uint32_t l = c ? cnf->literal_off[c] : 0;
+  if (l > ix->lmax) return fail(FR_EINVAL, "more literals than max_literals");
+  if (l && !cnf->terms) return fail(FR_EINVAL, "terms missing");
+  for (uint32_t i = 0; i < l; ++i)
+    if (cnf->terms[i] >= ix->cfg.vocab)
+      return fail(FR_EINVAL, "literal term " + std::to_string(cnf->terms[i]) + " >= vocab");
+  *n_c = c;
+  *n_l = l;
+  return FR_OK;
+}
+
+// Copy the CNF batch into a workspace's pinned staging and to the device.
+fr_status stage_cnf(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_q,
+                    const fr_cnf_batch* cnf, uint32_t n_c, uint32_t n_l) {
+  std::memcpy(w.h_co, cnf->clause_off, (n_q + 1) * 4);
+  if (n_c) std::memcpy(w.h_lo, cnf->literal_off, (n_c + 1) * 4);
+  else w.h_lo[0] = 0;
+  if (n_l) std::memcpy(w.h_terms, cnf->terms, n_l * 4);
+  FR_HIP(hipMemcpyAsync(w.clause_off, w.h_co, (n_q + 1) * 4, hipMemcpyHostToDevice, s));
+  FR_HIP(hipMemcpyAsync(w.literal_off, w.h_lo, (n_c + 1) * 4, hipMemcpyHostToDevice, s));
+  if (n_l) FR_HIP(hipMemcpyAsync(w.terms, w.h_terms, n_l * 4, hipMemcpyHostToDevice, s));
+  return FR_OK;
+}
+
+Workspace* acquire_ws(fr_index* ix, bool nowait, fr_status* st) {
+  const size_t n = ix->ws.size();
+  // prefer a workspace that is already free
+  for (size_t i = 0; i < n; ++i) {
+    Workspace& w = ix->ws[(ix->next_ws + i) % n];
+    if (!w.in_flight || hipEventQuery(w.done) == hipSuccess) {
+      w.in_flight = false;
+      ix->next_ws = (ix->next_ws + i + 1) % n;
+      *st = FR_OK;
+      return &w;
+    }
+  }
+  if (nowait) {
+    *st = fail(FR_EBUSY, "all workspaces are in use");
+    return nullptr;
+  }
+  Workspace& w = ix->ws[ix->next_ws];
+  ix->next_ws = (ix->next_ws + 1) % n;
+  if (hipEventSynchronize(w.done) != hipSuccess) {
+    ix->failed = true;
+    *st = fail(FR_EDEVICE, "hipEventSynchronize failed");
+    return nullptr;
+  }
+  w.in_flight = false;
+  *st = FR_OK;
+  return &w;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fr_last_error(void) { return g_err.c_str(); }
+
+fr_status fr_create(const fr_config* cfg, fr_index** out) {
+  if (!cfg || !out) return fail(FR_EINVAL, "null argument");
+  *out = nullptr;
+  if (cfg->dim < 1 || cfg->dim > 256) return fail(FR_EUNSUPPORTED, "dim must be 1..256");
+  if (cfg->vocab < 1 || cfg->vocab > (1u << 20)) return fail(FR_EINVAL, "vocab must be 1..2^20");
+  if (cfg->k_max < 1 || cfg->k_max > (uint32_t)kMaxR) return fail(FR_EINVAL, "k_max must be 1..4096");
+  if (cfg->capacity < 1 || cfg->capacity > (1ull << 32) - kGroup)
+    return fail(FR_EINVAL, "capacity must be 1..2^32-1024");
+  if (cfg->dtype != FR_F32 && cfg->dtype != FR_BF16 && cfg->dtype != FR_FP8_E4M3)
+    return fail(FR_EINVAL, "unknown dtype");
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || cfg->device < 0 || cfg->device >= n_dev)
+    return fail(FR_EDEVICE, "no such HIP device");
+  std::unique_ptr<fr_index> holder(new fr_index());
+  fr_index* ix = holder.get();
+  ix->cfg = *cfg;
+  ix->dt = (int)cfg->dtype;
+  ix->dim = cfg->dim;
+  ix->dpad = round_up(cfg->dim, 64);
+  ix->cap = (cfg->capacity + kGroup - 1) / kGroup * kGroup;
+  ix->r = cfg->rescore_r ? cfg->rescore_r : (uint32_t)kMaxR;
+  if (ix->dt != kF32 && (ix->r < cfg->k_max || ix->r > (uint32_t)kMaxR))
+    return fail(FR_EINVAL, "rescore_r must be k_max..4096");
+  ix->r_min = cfg->rescore_min ? std::min(cfg->rescore_min, ix->r) : ix->r;
+  ix->rmax = ix->dt == kF32 ? cfg->k_max : ix->r;
+  ix->qmax = cfg->max_batch ? cfg->max_batch : 1024;
+  if (ix->qmax > 65536) return fail(FR_EINVAL, "max_batch must be <= 65536");
+  ix->cmax = cfg->max_clauses ? cfg->max_clauses : 8 * ix->qmax;
+  ix->lmax = cfg->max_literals ? cfg->max_literals : 32 * ix->qmax;
+  ix->cand_cap = cfg->cand_cap ? cfg->cand_cap : std::max<uint32_t>(16384, 16 * ix->rmax);
+  if (ix->cand_cap < ix->rmax) return fail(FR_EINVAL, "cand_cap must be >= the selection size");
+  if (!scan_supported(ix->dt, ix->dpad, 1, 4))
+    return fail(FR_EUNSUPPORTED, "no scan kernel for this dtype/dim");
+  std::vector<void*>& D = ix->dev_owned;
+  std::vector<void*>& H = ix->host_owned;
+  auto cleanup = [&]() {
+    for (void* p : D) (void)hipFree(p);
+    for (void* p : H) (void)hipHostFree(p);
+    D.clear();
+    H.clear();
+  };
+#define FR_ALLOC(expr)                                                    \
+  do {                                                                    \
+    if ((expr) != hipSuccess) {                                           \
+      cleanup();                                                          \
+      return fail(FR_ENOMEM, std::string("allocation failed: ") + #expr); \
+    }                                                                     \
+  } while (0)
+  if (hipSetDevice(cfg->device) != hipSuccess) return fail(FR_EDEVICE, "hipSetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess)
+    return fail(FR_EDEVICE, "hipGetDeviceProperties failed");
+  ix->n_cu = prop.multiProcessorCount;
+  ix->n_wg = std::max(kXcds, ix->n_cu / kXcds * kXcds);
+  if (hipStreamCreateWithFlags(&ix->stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(FR_EDEVICE, "hipStreamCreate failed");
+
+  const uint64_t cap = ix->cap;
+  const size_t tb = tile_bytes(ix->dt, ix->dpad);
+  FR_ALLOC(dalloc(&ix->tiles, cap / kTile * tb, D));
+  if (ix->dt == kFP8) FR_ALLOC(dalloc(&ix->xscale, cap, D));
+  if (ix->dt != kF32) FR_ALLOC(dalloc(&ix->master, cap * ix->dpad, D));
+  FR_ALLOC(dalloc(&ix->slot_ids, cap, D));
+  FR_ALLOC(dalloc(&ix->live, cap / 64, D));
+  FR_ALLOC(dalloc(&ix->bits, cap / kGroup * (uint64_t)cfg->vocab * kWords, D));
+  FR_ALLOC(dalloc(&ix->norm_max, 1, D));
+  FR_ALLOC(dalloc(&ix->d_flag, 1, D));
+  ix->stage_rows = std::min<uint64_t>(cap, 1u << 18);
+  ix->stage_terms = ix->stage_rows * 64;
+  FR_ALLOC(dalloc(&ix->d_rows, ix->stage_rows * ix->dim, D));
+  FR_ALLOC(dalloc(&ix->d_off, ix->stage_rows + 1, D));
+  FR_ALLOC(dalloc(&ix->d_tl, ix->stage_terms, D));
+  FR_ALLOC(dalloc(&ix->d_ids, ix->stage_rows, D));
+  FR_ALLOC(dalloc(&ix->d_slots, ix->stage_rows, D));
+  FR_ALLOC(halloc(&ix->h_flag, 1, H));
+
+  const uint32_t nws = cfg->n_workspaces ? cfg->n_workspaces : 1;
+  ix->ws.resize(nws);
+  const uint32_t qm = ix->qmax, qpad = round_up(qm, kTile);
+  for (auto& w : ix->ws) {
+    FR_ALLOC(dalloc(&w.qrow, (size_t)qm * ix->dpad, D));
+    FR_ALLOC(dalloc(&w.qtiles, (size_t)qpad / kTile * tb, D));
+    FR_ALLOC(dalloc(&w.qscale, qm, D));
+    FR_ALLOC(dalloc(&w.qnorm, qm, D));
+    FR_ALLOC(dalloc(&w.clause_off, qm + 1, D));
+    FR_ALLOC(dalloc(&w.literal_off, ix->cmax + 1, D));
+    FR_ALLOC(dalloc(&w.terms, ix->lmax, D));
+    FR_ALLOC(dalloc(&w.k, qm, D));
+    FR_ALLOC(dalloc(&w.kp, qm, D));
+    FR_ALLOC(dalloc(&w.tau, qm, D));
+    FR_ALLOC(dalloc(&w.cnt, qm, D));
+    FR_ALLOC(dalloc(&w.smax, qm, D));
+    FR_ALLOC(dalloc(&w.hist, (size_t)qm * kHist, D));
+    FR_ALLOC(dalloc(&w.qlist, qm, D));
+    FR_ALLOC(dalloc(&w.qlist2, qm, D));
+    FR_ALLOC(dalloc(&w.ovf, qm, D));
+    FR_ALLOC(dalloc(&w.sel_cnt, qm, D));
+    FR_ALLOC(dalloc(&w.lit, (size_t)qm * 16, D));
+    FR_ALLOC(dalloc(&w.linfo, qm, D));
+    FR_ALLOC(dalloc(&w.desc, 4, D));
+    FR_ALLOC(dalloc(&w.work, kXcds, D));
+    FR_ALLOC(dalloc(&w.hlo, qm, D));
+    FR_ALLOC(dalloc(&w.hinvw, qm, D));
+    FR_ALLOC(dalloc(&w.nmatch, qm, D));
+    FR_ALLOC(dalloc(&w.cand_key, (size_t)qm * ix->cand_cap, D));
+    FR_ALLOC(dalloc(&w.cand_slot, (size_t)qm * ix->cand_cap, D));
+    FR_ALLOC(dalloc(&w.sel_key, (size_t)qm * ix->rmax, D));
+    FR_ALLOC(dalloc(&w.sel_slot, (size_t)qm * ix->rmax, D));
+    FR_ALLOC(dalloc(&w.out_ids, (size_t)qm * cfg->k_max, D));
+    FR_ALLOC(dalloc(&w.out_scores, (size_t)qm * cfg->k_max, D));
+    FR_ALLOC(dalloc(&w.out_count, qm, D));
+    FR_ALLOC(dalloc(&w.out_nmatch, qm, D));
+    FR_ALLOC(halloc(&w.h_q, (size_t)qm * ix->dpad, H));
+    FR_ALLOC(halloc(&w.h_co, qm + 1, H));
+    FR_ALLOC(halloc(&w.h_lo, ix->cmax + 1, H));
+    FR_ALLOC(halloc(&w.h_terms, ix->lmax, H));
+    FR_ALLOC(halloc(&w.h_k, qm, H));
+    FR_ALLOC(halloc(&w.h_desc, 4, H));
+    FR_ALLOC(halloc(&w.h_ids, (size_t)qm * cfg->k_max, H));
+    FR_ALLOC(halloc(&w.h_scores, (size_t)qm * cfg->k_max, H));
+    FR_ALLOC(halloc(&w.h_count, qm, H));
+    FR_ALLOC(halloc(&w.h_nmatch, qm, H));
+    FR_ALLOC(halloc(&w.h_cnt, qm, H));
+    FR_ALLOC(halloc(&w.h_selcnt, qm, H));
+    FR_ALLOC(halloc(&w.h_desc_out, 4, H));
+    bool ev_ok = hipEventCreate(&w.done) == hipSuccess;
+    for (int i = 0; i < Workspace::kRing && ev_ok; ++i)
+      ev_ok = hipEventCreate(&w.r0[i]) == hipSuccess && hipEventCreate(&w.r1[i]) == hipSuccess &&
+              hipEventCreate(&w.r2[i]) == hipSuccess;
+    if (!ev_ok) {
+      cleanup();
+      return fail(FR_EDEVICE, "hipEventCreate failed");
+    }
+    std::memset(w.h_q, 0, (size_t)qm * ix->dpad * sizeof(float));
+  }
+#undef FR_ALLOC
+  // initial state: empty corpus, zero padding everywhere
+  FR_HIP(launch_fill_u32((uint32_t*)ix->tiles, 0u, cap / kTile * tb / 4, ix->stream));
+  if (ix->master) FR_HIP(launch_fill_u32((uint32_t*)ix->master, 0u, cap * ix->dpad, ix->stream));
+  if (ix->xscale) FR_HIP(launch_fill_u32((uint32_t*)ix->xscale, 0x3F800000u, cap, ix->stream));
+  FR_HIP(launch_fill_u32(ix->slot_ids, 0xFFFFFFFFu, cap, ix->stream));
+  FR_HIP(launch_fill_u64(ix->live, 0ull, cap / 64, ix->stream));
+  FR_HIP(launch_fill_u64(ix->bits, 0ull, cap / kGroup * (uint64_t)cfg->vocab * kWords, ix->stream));
+  FR_HIP(launch_fill_u32(ix->norm_max, 0u, 1, ix->stream));
+  for (auto& w : ix->ws) {
+    FR_HIP(launch_fill_u32((uint32_t*)w.qrow, 0u, (size_t)qm * ix->dpad, ix->stream));
+    FR_HIP(launch_fill_u32((uint32_t*)w.qtiles, 0u, (size_t)qpad / kTile * tb / 4, ix->stream));
+  }
+  FR_HIP(hipStreamSynchronize(ix->stream));
+  ix->slot_id.assign(cap, 0xFFFFFFFFu);
+  *out = holder.release();
+  return FR_OK;
+}
+
+fr_status fr_destroy(fr_index* ix) {
+  if (!ix) return FR_OK;
+  {
+    std::lock_guard<std::mutex> lk(ix->mu);
+    (void)hipSetDevice(ix->cfg.device);
+    for (auto& w : ix->ws) {
+      if (w.done) {
+        (void)hipEventSynchronize(w.done);
+        (void)hipEventDestroy(w.done);
+      }
+      for (int i = 0; i < Workspace::kRing; ++i) {
+        if (w.r0[i]) (void)hipEventDestroy(w.r0[i]);
+        if (w.r1[i]) (void)hipEventDestroy(w.r1[i]);
+        if (w.r2[i]) (void)hipEventDestroy(w.r2[i]);
+      }
+    }
+    if (ix->stream) {
+      (void)hipStreamSynchronize(ix->stream);
+      (void)hipStreamDestroy(ix->stream);
+    }
+    for (void* p : ix->dev_owned) (void)hipFree(p);
+    for (void* p : ix->host_owned) (void)hipHostFree(p);
+  }
+  delete ix;
+  return FR_OK;
+}
+
+fr_status fr_load_corpus(fr_index* ix, uint64_t n, const float* emb, const uint32_t* ids,
+                         const uint64_t* term_off, const uint32_t* terms, uint32_t flags) {
+  if (!ix) return fail(FR_EINVAL, "null index");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (ix->failed) return fail(FR_EDEVICE, "index failed earlier");
+  FR_HIP(hipSetDevice(ix->cfg.device));
+  const bool dev = flags & FR_DEVICE_PTRS;
+  if (n > ix->cap || n > ix->cfg.capacity) return fail(FR_ECAPACITY, "n exceeds capacity");
+  if (n && (!ids || !term_off)) return fail(FR_EINVAL, "ids / term_off missing");
+  fr_status st = check_terms(ix, n, term_off, terms);
+  if (st != FR_OK) return st;
+  std::vector<uint32_t> hid(n);
+  if (n) {
+    if (dev) FR_HIP(hipMemcpy(hid.data(), ids, n * 4, hipMemcpyDeviceToHost));
+    else std::memcpy(hid.data(), ids, n * 4);
+  }
+  std::unordered_map<uint32_t, uint32_t> m;
+  m.reserve(n * 2 + 16);
+  for (uint64_t i = 0; i < n; ++i) {
+    if (hid[i] == 0xFFFFFFFFu) return fail(FR_EINVAL, "id 0xFFFFFFFF is reserved");
+    if (!m.emplace(hid[i], (uint32_t)i).second)
+      return fail(FR_EINVAL, "duplicate id " + std::to_string(hid[i]));
+  }
+  st = wait_all(ix);
+  if (st != FR_OK) return st;
+  st = check_rows(ix, emb, n, dev);
+  if (st != FR_OK) return st;
+  // reset the corpus
+  const uint64_t used = std::max<uint64_t>(ix->hwm, 1);
+  const uint64_t gused = (used + kGroup - 1) / kGroup;
+  FR_HIP(launch_fill_u64(ix->bits, 0ull, gused * (uint64_t)ix->cfg.vocab * kWords, ix->stream));
+  FR_HIP(launch_fill_u64(ix->live, 0ull, ix->cap / 64, ix->stream));
+  FR_HIP(launch_fill_u32(ix->slot_ids, 0xFFFFFFFFu, ix->cap, ix->stream));
+  FR_HIP(launch_fill_u32(ix->norm_max, 0u, 1, ix->stream));
+  ix->id2slot.clear();
+  ix->free_slots = decltype(ix->free_slots)();
+  std::fill(ix->slot_id.begin(), ix->slot_id.end(), 0xFFFFFFFFu);
+  ix->hwm = 0;
+  ix->n_live = 0;
+  st = write_docs(ix, n, emb, ids, term_off, terms, nullptr, 0, dev);
+  if (st != FR_OK) {
+    ix->failed = true;  // partially written corpus
+    return st;
+  }
+  ix->id2slot.swap(m);
+  for (uint64_t i = 0; i < n; ++i) ix->slot_id[i] = hid[i];
+  ix->hwm = n;
+  ix->n_live = n;
+  ix->epoch += 1;
+  return FR_OK;
+}
+
+fr_status fr_update_docs(fr_index* ix, uint64_t n_del, const uint32_t* del_ids, uint64_t n_ins,
+                         const uint32_t* ins_ids, const float* ins_emb,
+                         const uint64_t* ins_term_off, const uint32_t* ins_terms,
+                         uint64_t* out_epoch) {
+  if (!ix) return fail(FR_EINVAL, "null index");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (ix->failed) return fail(FR_EDEVICE, "index failed earlier");
+  FR_HIP(hipSetDevice(ix->cfg.device));
+  if (n_del && !del_ids) return fail(FR_EINVAL, "del_ids missing");
+  if (n_ins && (!ins_ids || !ins_term_off)) return fail(FR_EINVAL, "insert arrays missing");
+  // validate everything first (all-or-nothing)
+  std::unordered_set<uint32_t> dels;
+  dels.reserve(n_del * 2 + 16);
+  std::vector<uint32_t> del_slots(n_del);
+  for (uint64_t i = 0; i < n_del; ++i) {
+    auto it = ix->id2slot.find(del_ids[i]);
+    if (it == ix->id2slot.end())
+      return fail(FR_ENOTFOUND, "delete of unknown id " + std::to_string(del_ids[i]));
+    if (!dels.insert(del_ids[i]).second)
+      return fail(FR_ENOTFOUND, "id deleted twice in one call: " + std::to_string(del_ids[i]));
+    del_slots[i] = it->second;
+  }
+  std::unordered_set<uint32_t> ins;
+  ins.reserve(n_ins * 2 + 16);
+  for (uint64_t i = 0; i < n_ins; ++i) {
+    const uint32_t id = ins_ids[i];
+    if (id == 0xFFFFFFFFu) return fail(FR_EINVAL, "id 0xFFFFFFFF is reserved");
+    if (!ins.insert(id).second) return fail(FR_EDUPID, "id inserted twice: " + std::to_string(id));
+    if (ix->id2slot.count(id) && !dels.count(id))
+      return fail(FR_EDUPID, "insert of live id " + std::to_string(id));
+  }
+  if (ix->n_live - n_del + n_ins > ix->cfg.capacity)
+    return fail(FR_ECAPACITY, "update exceeds capacity");
+  fr_status st = check_terms(ix, n_ins, ins_term_off, ins_terms);
+  if (st != FR_OK) return st;
+  st = check_rows(ix, ins_emb, n_ins, false);
+  if (st != FR_OK) return st;
+  st = wait_all(ix);
+  if (st != FR_OK) return st;
+  // deletes: live bit, slot id, every term bit of the slot
+  for (uint64_t a0 = 0; a0 < n_del; a0 += ix->stage_rows) {
+    const uint64_t m = std::min<uint64_t>(ix->stage_rows, n_del - a0);
+    FR_HIP(hipMemcpyAsync(ix->d_slots, del_slots.data() + a0, m * 4, hipMemcpyHostToDevice, ix->stream));
+    LiveArgs la{};
+    la.slots = ix->d_slots;
+    la.n = m;
+    la.slot_ids = ix->slot_ids;
+    la.live = ix->live;
+    la.set = 0;
+    FR_HIP(launch_live(la, ix->stream));
+    FR_HIP(launch_clear_slot_terms(ix->d_slots, m, ix->bits, ix->cfg.vocab, ix->stream));
+    FR_HIP(hipStreamSynchronize(ix->stream));
+  }
+  for (uint64_t i = 0; i < n_del; ++i) {
+    ix->id2slot.erase(del_ids[i]);
+    ix->slot_id[del_slots[i]] = 0xFFFFFFFFu;
+    ix->free_slots.push(del_slots[i]);
+  }
+  ix->n_live -= n_del;
+  // inserts: lowest free slots first
+  std::vector<uint32_t> slots(n_ins);
+  for (uint64_t i = 0; i < n_ins; ++i) {
+    if (!ix->free_slots.empty()) {
+      slots[i] = ix->free_slots.top();
+      ix->free_slots.pop();
+    } else {
+      slots[i] = (uint32_t)ix->hwm++;
+    }
+  }
+  st = write_docs(ix, n_ins, ins_emb, ins_ids, ins_term_off, ins_terms, slots.data(), 0, false);
+  if (st != FR_OK) {
+    ix->failed = true;
+    return st;
+  }
+  for (uint64_t i = 0; i < n_ins; ++i) {
+    ix->id2slot[ins_ids[i]] = slots[i];
+    ix->slot_id[slots[i]] = ins_ids[i];
+  }
+  ix->n_live += n_ins;
+  ix->epoch += 1;
+  if (out_epoch) *out_epoch = ix->epoch;
+  return FR_OK;
+}
+
+fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_cnf_batch* cnf,
+                    const uint32_t* k, uint32_t* out_ids, float* out_scores, uint32_t* out_count,
+                    uint64_t* out_nmatch, void* stream, uint32_t flags) {
+  if (!ix) return fail(FR_EINVAL, "null index");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (ix->failed) return fail(FR_EDEVICE, "index failed earlier");
+  FR_HIP(hipSetDevice(ix->cfg.device));
+  const bool dev = flags & FR_DEVICE_PTRS;
+  if (stream && !dev) return fail(FR_EINVAL, "an asynchronous search needs FR_DEVICE_PTRS");
+  if (n_q > ix->qmax) return fail(FR_EINVAL, "n_q exceeds max_batch");
+  uint32_t n_c = 0, n_l = 0;
+  fr_status st = validate_cnf(ix, n_q, cnf, &n_c, &n_l);
+  if (st != FR_OK) return st;
+  if (n_q == 0) return FR_OK;
+  if (!queries || !k || !out_ids || !out_scores || !out_count || !out_nmatch)
+    return fail(FR_EINVAL, "null query or output pointer");
+  for (uint32_t q = 0; q < n_q; ++q)
+    if (k[q] > ix->cfg.k_max) return fail(FR_EINVAL, "k exceeds k_max");
+  Workspace* w = acquire_ws(ix, flags & FR_NOWAIT, &st);
+  if (!w) return st;
+  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
+  // inputs
+  w->h_desc[0] = n_q;
+  w->h_desc[1] = n_q;
+  w->h_desc[2] = 0;
+  w->h_desc[3] = 0;
+  FR_HIP(hipMemcpyAsync(w->desc, w->h_desc, 16, hipMemcpyHostToDevice, s));
+  std::memcpy(w->h_k, k, n_q * 4);
+  FR_HIP(hipMemcpyAsync(w->k, w->h_k, n_q * 4, hipMemcpyHostToDevice, s));
+  st = stage_cnf(ix, *w, s, n_q, cnf, n_c, n_l);
+  if (st != FR_OK) return st;
+  const size_t qbytes = (size_t)ix->dpad * 4;
+  if (dev) {
+    FR_HIP(hipMemcpy2DAsync(w->qrow, qbytes, queries, (size_t)ix->dim * 4, (size_t)ix->dim * 4,
+                            n_q, hipMemcpyDeviceToDevice, s));
+  } else {
+    for (uint32_t q = 0; q < n_q; ++q)
+      std::memcpy(w->h_q + (size_t)q * ix->dpad, queries + (size_t)q * ix->dim, (size_t)ix->dim * 4);
+    FR_HIP(hipMemcpyAsync(w->qrow, w->h_q, n_q * qbytes, hipMemcpyHostToDevice, s));
+  }
+  uint32_t* o_ids = dev ? out_ids : w->out_ids;
+  float* o_scores = dev ? out_scores : w->out_scores;
+  uint32_t* o_count = dev ? out_count : w->out_count;
+  unsigned long long* o_nm = dev ? (unsigned long long*)out_nmatch : w->out_nmatch;
+  st = enqueue_search(ix, *w, s, n_q, o_ids, o_scores, o_count, o_nm);
+  if (st != FR_OK) return st;
+  const size_t kk = (size_t)n_q * ix->cfg.k_max;
+  if (!dev) {
+    FR_HIP(hipMemcpyAsync(w->h_ids, w->out_ids, kk * 4, hipMemcpyDeviceToHost, s));
+    FR_HIP(hipMemcpyAsync(w->h_scores, w->out_scores, kk * 4, hipMemcpyDeviceToHost, s));
+    FR_HIP(hipMemcpyAsync(w->h_count, w->out_count, n_q * 4, hipMemcpyDeviceToHost, s));
+    FR_HIP(hipMemcpyAsync(w->h_nmatch, w->out_nmatch, n_q * 8, hipMemcpyDeviceToHost, s));
+  }
+  FR_HIP(hipMemcpyAsync(w->h_cnt, w->cnt, n_q * 4, hipMemcpyDeviceToHost, s));
+  FR_HIP(hipMemcpyAsync(w->h_selcnt, w->sel_cnt, n_q * 4, hipMemcpyDeviceToHost, s));
+  FR_HIP(hipMemcpyAsync(w->h_desc_out, w->desc, 16, hipMemcpyDeviceToHost, s));
+  FR_HIP(hipEventRecord(w->done, s));
+  w->in_flight = true;
+  // algorithmic bytes / flops of this batch (for statistics)
+  {
+    std::vector<uint32_t> t(cnf->terms, cnf->terms + n_l);
+    std::sort(t.begin(), t.end());
+    w->last_terms = (uint64_t)(std::unique(t.begin(), t.end()) - t.begin());
+    w->last_live = ix->n_live;
+    const double per_doc = (double)ix->dpad * elem_bytes(ix->dt) + (ix->dt == kFP8 ? 4.0 : 0.0);
+    w->last_alg_bytes = (double)ix->n_live * per_doc + (double)ix->n_live * w->last_terms / 8.0 +
+                        (double)ix->hwm / 8.0 + (double)n_q * ix->cfg.k_max * 8.0;
+    w->last_alg_flops = 2.0 * ix->dim * n_q * (double)ix->n_live;
+  }
+  w->last_nq = n_q;
+  ix->last_ws = (size_t)(w - ix->ws.data());
+  ix->have_last = true;
+  if (stream) return FR_OK;
+  FR_HIP(hipEventSynchronize(w->done));
+  w->in_flight = false;
+  bool failed_q = false;
+  const uint32_t* cnts = dev ? nullptr : w->h_count;
+  if (!dev) {
+    std::memcpy(out_ids, w->h_ids, kk * 4);
+    std::memcpy(out_scores, w->h_scores, kk * 4);
+    std::memcpy(out_count, w->h_count, n_q * 4);
+    std::memcpy(out_nmatch, w->h_nmatch, n_q * 8);
+  }
+  if (cnts) {
+    for (uint32_t q = 0; q < n_q; ++q) failed_q |= cnts[q] == 0xFFFFFFFFu;
+  }
+  if (failed_q)
+    return fail(FR_EUNSUPPORTED,
+                "a query had more tied candidates than the candidate buffer holds (raise cand_cap)");
+  return FR_OK;
+}
+
+fr_status fr_stats(fr_index* ix, fr_search_stats* out) {
+  if (!ix || !out) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (!ix->have_last) return fail(FR_EINVAL, "no search yet");
+  Workspace& w = ix->ws[ix->last_ws];
+  if (hipEventSynchronize(w.done) != hipSuccess) return fail(FR_EDEVICE, "event");
+  fr_search_stats s{};
+  s.n_queries = w.last_nq;
+  uint64_t cands = 0;
+  const uint32_t passes = w.h_desc_out[2] ? 2 : 1;
+  double gathers = 0;
+  for (uint32_t q = 0; q < w.last_nq; ++q) {
+    cands += std::min(w.h_cnt[q], ix->cand_cap);
+    if (ix->dt != kF32) gathers += (double)w.h_selcnt[q] * ix->dpad * 4.0;
+  }
+  s.n_passes = passes;
+  s.candidates = cands;
+  s.n_live = w.last_live;
+  s.n_terms_batch = w.last_terms;
+  s.alg_bytes = w.last_alg_bytes + gathers;
+  s.alg_flops = w.last_alg_flops;
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, w.e_scan0, w.e_scan1) == hipSuccess) s.ms_scan = ms;
+  if (hipEventElapsedTime(&ms, w.e_scan0, w.e_end) == hipSuccess) s.ms_total = ms;
+  *out = s;
+  return FR_OK;
+}
+
+fr_status fr_timings(fr_index* ix, uint32_t max, float* scan_ms, float* total_ms, uint32_t* n) {
+  if (!ix || !n) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  const size_t h = ix->history.size();
+  const size_t m = std::min<size_t>(max, h);
+  for (size_t i = 0; i < m; ++i) {
+    const auto& e = ix->history[h - m + i];
+    Workspace& w = ix->ws[e.first];
+    if (hipEventSynchronize(w.r2[e.second]) != hipSuccess) return fail(FR_EDEVICE, "event");
+    float a = 0, b = 0;
+    if (hipEventElapsedTime(&a, w.r0[e.second], w.r1[e.second]) != hipSuccess ||
+        hipEventElapsedTime(&b, w.r0[e.second], w.r2[e.second]) != hipSuccess)
+      return fail(FR_EDEVICE, "hipEventElapsedTime");
+    if (scan_ms) scan_ms[i] = a;
+    if (total_ms) total_ms[i] = b;
+  }
+  *n = (uint32_t)m;
+  return FR_OK;
+}
+
+fr_status fr_info(fr_index* ix, uint64_t* n_live, uint64_t* epoch, uint64_t* n_slots) {
+  if (!ix) return fail(FR_EINVAL, "null index");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (n_live) *n_live = ix->n_live;
+  if (epoch) *epoch = ix->epoch;
+  if (n_slots) *n_slots = ix->hwm;
+  return FR_OK;
+}
+
+fr_status fr_debug_masks(fr_index* ix, const fr_cnf_batch* cnf, uint64_t* out_bits,
+                         uint64_t n_words_per_query) {
+  if (!ix || !cnf || !out_bits) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (ix->failed) return fail(FR_EDEVICE, "index failed earlier");
+  FR_HIP(hipSetDevice(ix->cfg.device));
+  const uint32_t n_q = cnf->n_queries;
+  if (n_q > ix->qmax) return fail(FR_EINVAL, "n_q exceeds max_batch");
+  uint32_t n_c = 0, n_l = 0;
+  fr_status st = validate_cnf(ix, n_q, cnf, &n_c, &n_l);
+  if (st != FR_OK) return st;
+  const uint64_t need = (ix->hwm + 63) / 64;
+  if (n_words_per_query < need) return fail(FR_EINVAL, "n_words_per_query < ceil(n_slots/64)");
+  if (!n_q || !need) return FR_OK;
+  st = wait_all(ix);
+  if (st != FR_OK) return st;
+  Workspace& w = ix->ws[0];
+  st = stage_cnf(ix, w, ix->stream, n_q, cnf, n_c, n_l);
+  if (st != FR_OK) return st;
+  // testing entry point: a temporary output buffer
+  unsigned long long* d_out = nullptr;
+  FR_HIP(hipMalloc(&d_out, n_q * need * 8));
+  MaskArgs ma{};
+  ma.live = ix->live;
+  ma.bits = ix->bits;
+  ma.vocab = ix->cfg.vocab;
+  ma.n_q = n_q;
+  ma.n_words = need;
+  ma.clause_off = w.clause_off;
+  ma.literal_off = w.literal_off;
+  ma.terms = w.terms;
+  ma.out = d_out;
+  hipError_t e = launch_masks(ma, n_q * need, ix->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ix->stream);
+  std::vector<uint64_t> tmp(n_q * need);
+  if (e == hipSuccess) e = hipMemcpy(tmp.data(), d_out, n_q * need * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) {
+    ix->failed = true;
+    return fail(FR_EDEVICE, std::string("masks: ") + hipGetErrorString(e));
+  }
+  for (uint32_t q = 0; q < n_q; ++q)
+    std::memcpy(out_bits + q * n_words_per_query, tmp.data() + q * need, need * 8);
+  return FR_OK;
+}
+
+fr_status fr_debug_slots(fr_index* ix, uint32_t* out_ids, uint64_t n) {
+  if (!ix || !out_ids) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  for (uint64_t i = 0; i < n; ++i) out_ids[i] = i < ix->slot_id.size() ? ix->slot_id[i] : 0xFFFFFFFFu;
+  return FR_OK;
+}
+
+fr_status fr_debug_candidates(fr_index* ix, uint32_t n_q, uint32_t* out_ids, float* out_scores,
+                              uint32_t* out_count) {
+  if (!ix || !out_ids || !out_scores || !out_count) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (!ix->have_last) return fail(FR_EINVAL, "no search yet");
+  Workspace& w = ix->ws[ix->last_ws];
+  if (n_q > w.last_nq) return fail(FR_EINVAL, "n_q exceeds the last batch");
+  FR_HIP(hipEventSynchronize(w.done));
+  const size_t R = ix->rmax;
+  std::vector<unsigned long long> keys((size_t)n_q * R);
+  std::vector<uint32_t> cnt(n_q);
+  FR_HIP(hipMemcpy(keys.data(), w.sel_key, keys.size() * 8, hipMemcpyDeviceToHost));
+  FR_HIP(hipMemcpy(cnt.data(), w.sel_cnt, n_q * 4, hipMemcpyDeviceToHost));
+  for (uint32_t q = 0; q < n_q; ++q) {
+    out_count[q] = cnt[q];
+    for (size_t r = 0; r < R; ++r) {
+      const bool ok = r < cnt[q];
+      const unsigned long long key = keys[q * R + r];
+      const uint32_t k32 = (uint32_t)(key >> 32);
+      uint32_t u = (k32 & 0x80000000u) ? (k32 & 0x7FFFFFFFu) : ~k32;
+      float f;
+      std::memcpy(&f, &u, 4);
+      out_ids[q * R + r] = ok ? 0xFFFFFFFFu - (uint32_t)key : 0xFFFFFFFFu;
+      out_scores[q * R + r] = ok ? f : -INFINITY;
+    }
+  }
+  return FR_OK;
+}
+
+fr_status fr_debug_rows(fr_index* ix, uint64_t slot0, uint64_t n, void* out_codes,
+                        float* out_scales) {
+  if (!ix || !out_codes) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (ix->failed) return fail(FR_EDEVICE, "index failed earlier");
+  if (slot0 + n > ix->cap) return fail(FR_EINVAL, "slot range outside capacity");
+  if (!n) return FR_OK;
+  FR_HIP(hipSetDevice(ix->cfg.device));
+  fr_status st = wait_all(ix);
+  if (st != FR_OK) return st;
+  const int es = elem_bytes(ix->dt);
+  const size_t tb = tile_bytes(ix->dt, ix->dpad);
+  const uint64_t t0 = slot0 / kTile, t1 = (slot0 + n + kTile - 1) / kTile;
+  std::vector<uint8_t> raw((t1 - t0) * tb);
+  FR_HIP(hipMemcpy(raw.data(), ix->tiles + t0 * tb, raw.size(), hipMemcpyDeviceToHost));
+  uint8_t* out = (uint8_t*)out_codes;
+  const int hd = (int)ix->dpad / 2, pc = 16 / es;
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint64_t slot = slot0 + i;
+    const uint8_t* tile = raw.data() + (slot / kTile - t0) * tb;
+    const int r = (int)(slot % kTile);
+    for (int e = 0; e < (int)ix->dpad; ++e) {
+      const int h = e / hd, p = e % hd, j = p / pc, idx = p % pc;
+      std::memcpy(out + (i * ix->dpad + e) * es, tile + (size_t)(j * 64 + h * 32 + r) * 16 + idx * es,
+                  es);
+    }
+  }
+  if (out_scales) {
+    if (ix->xscale) FR_HIP(hipMemcpy(out_scales, ix->xscale + slot0, n * 4, hipMemcpyDeviceToHost));
+    else for (uint64_t i = 0; i < n; ++i) out_scales[i] = 1.0f;
+  }
+  return FR_OK;
+}
+
+fr_status fr_set_tiling(fr_index* ix, uint32_t query_blocks, uint32_t waves,
+                        uint32_t groups_per_item) {
+  if (!ix) return fail(FR_EINVAL, "null index");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (query_blocks || waves) {
+    if (!scan_supported(ix->dt, ix->dpad, (int)query_blocks, (int)waves))
+      return fail(FR_EUNSUPPORTED, "no scan kernel with that tiling");
+    ix->qb = (int)query_blocks;
+    ix->nw = (int)waves;
+  } else {
+    ix->qb = ix->nw = 0;
+  }
+  ix->gpi = (int)std::min<uint32_t>(groups_per_item, 64);
+  return FR_OK;
+}
+
+fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr_cnf_batch* cnf,
+                      const uint32_t* k, uint32_t flags, uint32_t* out_query_blocks,
+                      uint32_t* out_waves, uint32_t* out_groups) {
+  if (!ix) return fail(FR_EINVAL, "null index");
+  if (flags & FR_DEVICE_PTRS) return fail(FR_EINVAL, "autotune takes host pointers");
+  const size_t kk = (size_t)n_q * ix->cfg.k_max;
+  std::vector<uint32_t> ids(kk), cnt(n_q);
+  std::vector<float> sc(kk);
+  std::vector<uint64_t> nm(n_q);
+  float best = INFINITY;
+  int best_qb = 0, best_nw = 0, best_g = 0;
+  const int saved_qb = ix->qb, saved_nw = ix->nw, saved_g = ix->gpi;
+  const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
+  for (int nw : {4, 8}) {
+    for (int qb : {1, 2, 4}) {
+      if (!scan_supported(ix->dt, ix->dpad, qb, nw)) continue;
+      const uint32_t qt = 32u * qb * nw;
+      if (qt > round_up(std::max<uint32_t>(n_q, 1), 128) && qt > 128) continue;
+      for (int g : {0, 1, 2, 4, 8}) {
+        ix->qb = qb;
+        ix->nw = nw;
+        ix->gpi = g;
+        if (g && g == pick_gpi(ix, n_q, (int)qt, n_groups)) continue;
+        float tot = 0;
+        for (int rep = 0; rep < 3; ++rep) {
+          fr_status st = fr_search(ix, n_q, queries, cnf, k, ids.data(), sc.data(), cnt.data(),
+                                   nm.data(), nullptr, 0);
+          if (st != FR_OK) {
+            ix->qb = saved_qb;
+            ix->nw = saved_nw;
+            ix->gpi = saved_g;
+            return st;
+          }
+          fr_search_stats s{};
+          if (fr_stats(ix, &s) == FR_OK && rep > 0) tot += s.ms_total;
+        }
+        if (tot < best) {
+          best = tot;
+          best_qb = qb;
+          best_nw = nw;
+          best_g = g;
+        }
+      }
+    }
+  }
+  ix->qb = best_qb;
+  ix->nw = best_nw;
+  ix->gpi = best_g;
+  if (out_query_blocks) *out_query_blocks = (uint32_t)best_qb;
+  if (out_waves) *out_waves = (uint32_t)best_nw;
+  if (out_groups) *out_groups = (uint32_t)best_g;
+  return FR_OK;
+}
+
+}  // extern "C"
