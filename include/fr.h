@@ -59,6 +59,10 @@ typedef enum {
 /* flags */
 #define FR_DEVICE_PTRS 1u  /* data pointers are device pointers (see above) */
 #define FR_NOWAIT      2u  /* fr_search: return FR_EBUSY instead of waiting for a workspace */
+#define FR_GRAPH       4u  /* fr_search: replay the workspace's captured HIP graph of the
+                              device sequence (captured on first use and again whenever
+                              the tiling, corpus extent or output pointers change); the
+                              call's fr_timings entry then has scan_ms == total_ms */
 
 typedef struct {
   uint64_t capacity;       /* maximum live documents (slots); rounded up to 1024 */

@@ -4,4 +4,4 @@ A C-ABI library of hand-written HIP kernels (``include/fr.h``,
 ``csrc/``) with a thin ctypes binding.  See ``binding.Index``.
 """
 from .binding import (Cnf, FrError, Index, SearchResult, lib,  # noqa: F401
-                      FR_DEVICE_PTRS, FR_NOWAIT, STATUS_NAMES, SYMBOLS)
+                      FR_DEVICE_PTRS, FR_GRAPH, FR_NOWAIT, STATUS_NAMES, SYMBOLS)

@@ -16,6 +16,7 @@ constexpr int kHist = kNBC + kNBF;   // u32 counters per query histogram
 constexpr int kXcds = 8;             // work queues (one per XCD)
 constexpr int kSelCap = 8192;        // candidates sorted in LDS by the select kernel
 constexpr int kMaxR = 4096;          // largest K / R handled by select and rescore
+constexpr int kLits = 12;            // literals per query in the scan's fast mask path
 constexpr uint32_t kKeyNegInf = 0x007FFFFFu;  // order key of -inf
 constexpr uint32_t kKeyPosInf = 0xFF800000u;  // order key of +inf
 
@@ -85,9 +86,9 @@ struct PrepArgs {
   uint32_t* n_list2;       // device: rerun list length (zeroed)
   uint32_t* work;          // kXcds counters (zeroed)
   uint32_t* ovf;           // per-query overflow flag
-  // CNF of the batch and its per-query literal table (out): up to 16 term
-  // ids per query, and an info word: bits 0-4 literal count (<= 16), 8-23
-  // first-literal-of-clause flags, 24 an empty clause, 25 more than 16
+  // CNF of the batch and its per-query literal table (out): kLits term ids
+  // per query, and an info word: bits 0-4 literal count (<= kLits), 8-23
+  // first-literal-of-clause flags, 24 an empty clause, 25 more than kLits
   // literals (evaluated from the CSR arrays instead), 26 at least one clause.
   const uint32_t* clause_off;
   const uint32_t* literal_off;

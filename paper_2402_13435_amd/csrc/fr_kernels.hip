@@ -98,6 +98,13 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, uint64_t n) {
     p[i] = v;
 }
 
+// Every launcher refuses a null pointer the kernel would dereference, so a
+// host-side wiring mistake becomes an error status instead of a GPU fault.
+#define FR_REQUIRE(p) \
+  do {                \
+    if (!(p)) return hipErrorInvalidValue; \
+  } while (0)
+
 static inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 65535u * 4) {
   uint64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
@@ -176,6 +183,10 @@ __global__ __launch_bounds__(256) void k_tile_rows(TileRowsArgs a) {
 
 hipError_t launch_tile_rows(const TileRowsArgs& a, hipStream_t s) {
   if (!a.n) return hipSuccess;
+  FR_REQUIRE(a.rows);
+  FR_REQUIRE(a.tiles);
+  if (a.dt == kFP8) FR_REQUIRE(a.scale);
+  if (a.dpad % 64 || a.dpad > 256 || a.dim > a.dpad) return hipErrorInvalidValue;
   const dim3 g((unsigned)((a.n + 3) / 4)), b(256);
   switch (a.dt) {
     case kF32: hipLaunchKernelGGL(k_tile_rows<kF32>, g, b, 0, s, a); break;
@@ -202,6 +213,9 @@ __global__ __launch_bounds__(256) void k_terms(TermArgs a) {
 }
 hipError_t launch_terms(const TermArgs& a, hipStream_t s) {
   if (!a.n) return hipSuccess;
+  FR_REQUIRE(a.off);
+  FR_REQUIRE(a.terms);
+  FR_REQUIRE(a.bits);
   hipLaunchKernelGGL(k_terms, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -222,6 +236,9 @@ __global__ __launch_bounds__(256) void k_live(LiveArgs a) {
 }
 hipError_t launch_live(const LiveArgs& a, hipStream_t s) {
   if (!a.n) return hipSuccess;
+  FR_REQUIRE(a.slot_ids);
+  FR_REQUIRE(a.live);
+  if (a.set) FR_REQUIRE(a.ids);
   hipLaunchKernelGGL(k_live, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -243,6 +260,8 @@ hipError_t launch_clear_slot_terms(const uint32_t* slots, uint64_t n, uint64_t* 
                                    uint32_t vocab, hipStream_t s) {
   const uint64_t total = n * vocab;
   if (!total) return hipSuccess;
+  FR_REQUIRE(slots);
+  FR_REQUIRE(bits);
   hipLaunchKernelGGL(k_clear_slot_terms, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      slots, n, bits, vocab);
   return hipGetLastError();
@@ -257,6 +276,8 @@ __global__ void k_check_finite(const float* x, uint64_t n, uint32_t* flag) {
 }
 hipError_t launch_check_finite(const float* x, uint64_t n, uint32_t* flag, hipStream_t s) {
   if (!n) return hipSuccess;
+  FR_REQUIRE(x);
+  FR_REQUIRE(flag);
   hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, x, n, flag);
   return hipGetLastError();
 }
@@ -293,6 +314,12 @@ __global__ __launch_bounds__(256) void k_masks(MaskArgs a, uint64_t total) {
 }
 hipError_t launch_masks(const MaskArgs& a, uint64_t total, hipStream_t s) {
   if (!total) return hipSuccess;
+  FR_REQUIRE(a.live);
+  FR_REQUIRE(a.bits);
+  FR_REQUIRE(a.clause_off);
+  FR_REQUIRE(a.literal_off);
+  FR_REQUIRE(a.terms);
+  FR_REQUIRE(a.out);
   hipLaunchKernelGGL(k_masks, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, total);
   return hipGetLastError();
 }
@@ -332,23 +359,46 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   const uint32_t l0 = c0 < c1 ? a.literal_off[c0] : 0u, l1 = c0 < c1 ? a.literal_off[c1] : 0u;
   const uint32_t nl = l1 - l0;
   uint32_t starts = 0, n = 0, empty = 0;
-  uint32_t* lit = a.lit + (uint64_t)q * 16;
+  constexpr uint32_t L = kLits;
+  uint32_t* lit = a.lit + (uint64_t)q * L;
   for (uint32_t c = c0; c < c1; ++c) {
     const uint32_t a0 = a.literal_off[c], a1 = a.literal_off[c + 1];
     if (a0 == a1) empty = 1u;
     for (uint32_t l = a0; l < a1; ++l) {
-      if (n < 16u) {
+      if (n < L) {
         if (l == a0) starts |= 1u << n;
         lit[n] = a.terms[l];
       }
       ++n;
     }
   }
-  for (uint32_t i = n; i < 16u; ++i) lit[i] = 0u;
-  a.linfo[q] = (nl > 16u ? 16u : nl) | (starts << 8) | (empty << 24) | ((nl > 16u ? 1u : 0u) << 25) |
+  for (uint32_t i = n; i < L; ++i) lit[i] = 0u;
+  a.linfo[q] = (nl > L ? L : nl) | (starts << 8) | (empty << 24) | ((nl > L ? 1u : 0u) << 25) |
                ((c1 > c0 ? 1u : 0u) << 26);
 }
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
+  FR_REQUIRE(a.n_dev);
+  FR_REQUIRE(a.k);
+  FR_REQUIRE(a.kp);
+  FR_REQUIRE(a.qnorm);
+  FR_REQUIRE(a.norm_max);
+  FR_REQUIRE(a.tau);
+  FR_REQUIRE(a.cnt);
+  FR_REQUIRE(a.smax);
+  FR_REQUIRE(a.hist);
+  FR_REQUIRE(a.hlo);
+  FR_REQUIRE(a.hinvw);
+  FR_REQUIRE(a.nmatch);
+  FR_REQUIRE(a.qlist);
+  FR_REQUIRE(a.n_list);
+  FR_REQUIRE(a.n_list2);
+  FR_REQUIRE(a.work);
+  FR_REQUIRE(a.ovf);
+  FR_REQUIRE(a.clause_off);
+  FR_REQUIRE(a.literal_off);
+  FR_REQUIRE(a.terms);
+  FR_REQUIRE(a.lit);
+  FR_REQUIRE(a.linfo);
   hipLaunchKernelGGL(k_prep, dim3(grid_for(a.max_q ? a.max_q : 1, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -372,6 +422,17 @@ __global__ __launch_bounds__(256) void k_rerun(RerunArgs a) {
   for (int i = 0; i < kHist; ++i) h[i] = 0u;
 }
 hipError_t launch_rerun(const RerunArgs& a, hipStream_t s) {
+  FR_REQUIRE(a.n_dev);
+  FR_REQUIRE(a.ovf);
+  FR_REQUIRE(a.qlist2);
+  FR_REQUIRE(a.n_list2);
+  FR_REQUIRE(a.tau);
+  FR_REQUIRE(a.cnt);
+  FR_REQUIRE(a.smax);
+  FR_REQUIRE(a.hist);
+  FR_REQUIRE(a.hlo);
+  FR_REQUIRE(a.hinvw);
+  FR_REQUIRE(a.work);
   hipLaunchKernelGGL(k_rerun, dim3(grid_for(a.max_q ? a.max_q : 1, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -380,6 +441,7 @@ __global__ void k_zero_work(uint32_t* w) {
   if (threadIdx.x < kXcds) w[threadIdx.x] = 0u;
 }
 hipError_t launch_zero_work(uint32_t* work, hipStream_t s) {
+  FR_REQUIRE(work);
   hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(64), 0, s, work);
   return hipGetLastError();
 }
@@ -461,7 +523,6 @@ __device__ __forceinline__ void load_tile(TileBuf<DT, CH>& t, const uint8_t* __r
 // Literal table of one query (built by the prep kernel): up to kLits term
 // ids and a packed info word (see PrepArgs).  A lane evaluates the CNF of a
 // query over one 64-document word with all literal loads in flight at once.
-constexpr int kLits = 12;
 __device__ __forceinline__ bool lit_slow(uint32_t info) { return (info >> 25) & 1u; }
 
 struct MaskJob {
@@ -896,6 +957,34 @@ bool scan_supported(int dt, int dpad, int qb, int nw) {
 
 hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int n_wg,
                        hipStream_t s) {
+  FR_REQUIRE(a.tiles);
+  FR_REQUIRE(a.slot_ids);
+  FR_REQUIRE(a.live);
+  FR_REQUIRE(a.bits);
+  FR_REQUIRE(a.qtiles);
+  FR_REQUIRE(a.qlist);
+  FR_REQUIRE(a.n_list);
+  FR_REQUIRE(a.kp);
+  FR_REQUIRE(a.tau);
+  FR_REQUIRE(a.cnt);
+  FR_REQUIRE(a.smax);
+  FR_REQUIRE(a.hist);
+  FR_REQUIRE(a.hlo);
+  FR_REQUIRE(a.hinvw);
+  FR_REQUIRE(a.cand_key);
+  FR_REQUIRE(a.cand_slot);
+  FR_REQUIRE(a.nmatch);
+  FR_REQUIRE(a.work);
+  FR_REQUIRE(a.clause_off);
+  FR_REQUIRE(a.literal_off);
+  FR_REQUIRE(a.terms);
+  FR_REQUIRE(a.lit);
+  FR_REQUIRE(a.linfo);
+  if (dt == kFP8) {
+    FR_REQUIRE(a.xscale);
+    FR_REQUIRE(a.qscale);
+  }
+  if (a.gpi < 1 || n_wg < 1) return hipErrorInvalidValue;
 #define FR_LAUNCH(D, P, Q, W)                                                          \
   if (dt == D && dpad == P && qb == Q && nw == W) {                                    \
     hipLaunchKernelGGL((k_scan<D, P, Q, W>), dim3(n_wg), dim3(W * 64), 0, s, a);       \
@@ -1059,6 +1148,26 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
 
 hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
   if (!a.max_list) return hipSuccess;
+  FR_REQUIRE(a.qlist);
+  FR_REQUIRE(a.n_list);
+  FR_REQUIRE(a.kp);
+  FR_REQUIRE(a.tau);
+  FR_REQUIRE(a.cnt);
+  FR_REQUIRE(a.cand_key);
+  FR_REQUIRE(a.cand_slot);
+  FR_REQUIRE(a.sel_key);
+  FR_REQUIRE(a.sel_slot);
+  FR_REQUIRE(a.sel_cnt);
+  FR_REQUIRE(a.ovf);
+  if (a.rmax > (uint32_t)kMaxR || a.rmax < 1) return hipErrorInvalidValue;
+  if (a.write_out) {
+    FR_REQUIRE(a.k);
+    FR_REQUIRE(a.out_ids);
+    FR_REQUIRE(a.out_scores);
+    FR_REQUIRE(a.out_count);
+    FR_REQUIRE(a.nmatch);
+    FR_REQUIRE(a.out_nmatch);
+  }
   hipLaunchKernelGGL(k_select, dim3(a.max_list), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -1129,6 +1238,20 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
 
 hipError_t launch_rescore(const RescoreArgs& a, hipStream_t s) {
   if (!a.max_q) return hipSuccess;
+  FR_REQUIRE(a.n_dev);
+  FR_REQUIRE(a.ovf);
+  FR_REQUIRE(a.master);
+  FR_REQUIRE(a.qrows);
+  FR_REQUIRE(a.sel_key);
+  FR_REQUIRE(a.sel_slot);
+  FR_REQUIRE(a.sel_cnt);
+  FR_REQUIRE(a.k);
+  FR_REQUIRE(a.out_ids);
+  FR_REQUIRE(a.out_scores);
+  FR_REQUIRE(a.out_count);
+  FR_REQUIRE(a.nmatch);
+  FR_REQUIRE(a.out_nmatch);
+  if (a.rmax > (uint32_t)kMaxR || a.dpad > 256) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rescore, dim3(a.max_q), dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -118,6 +118,11 @@ struct Workspace {
   static constexpr int kRing = 64;
   hipEvent_t r0[kRing] = {}, r1[kRing] = {}, r2[kRing] = {};
   uint64_t n_calls = 0;
+  // captured search sequence (FR_GRAPH), valid for one tiling / corpus
+  // extent / output binding
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t gkey[8] = {};
   bool in_flight = false;
   uint32_t last_nq = 0;
   double last_alg_bytes = 0, last_alg_flops = 0;
@@ -316,12 +321,9 @@ int pick_gpi(const fr_index* ix, uint32_t n_q, int qt, uint32_t n_groups) {
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 16));
 }
 
-fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_q,
-                         uint32_t* o_ids, float* o_scores, uint32_t* o_count,
-                         unsigned long long* o_nmatch) {
-  int qb = 1, nw = 4;
-  pick_tiling(ix, n_q, &qb, &nw);
-  const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
+fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int nw, int gpi,
+                         uint32_t n_groups, bool timing, uint32_t* o_ids, float* o_scores,
+                         uint32_t* o_count, unsigned long long* o_nmatch) {
   TileRowsArgs ta{};
   ta.rows = w.qrow;
   ta.n = ix->qmax;
@@ -387,22 +389,16 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_q
   sa.cap = ix->cand_cap;
   sa.nmatch = w.nmatch;
   sa.work = w.work;
-  sa.gpi = (uint32_t)pick_gpi(ix, n_q, 32 * qb * nw, n_groups);
+  sa.gpi = (uint32_t)gpi;
   sa.count_matches = 1;
   sa.clause_off = w.clause_off;
   sa.literal_off = w.literal_off;
   sa.terms = w.terms;
-  const int slot = (int)(w.n_calls % Workspace::kRing);
-  w.e_scan0 = w.r0[slot];
-  w.e_scan1 = w.r1[slot];
-  w.e_end = w.r2[slot];
-  w.n_calls += 1;
-  ix->history.emplace_back((uint32_t)(&w - ix->ws.data()), (uint32_t)slot);
-  if (ix->history.size() > (size_t)Workspace::kRing)
-    ix->history.erase(ix->history.begin(), ix->history.begin() + (ix->history.size() - Workspace::kRing));
-  FR_HIP(hipEventRecord(w.e_scan0, s));
+  sa.lit = w.lit;
+  sa.linfo = w.linfo;
+  if (timing) FR_HIP(hipEventRecord(w.e_scan0, s));
   FR_HIP(launch_scan(sa, ix->dt, ix->dpad, qb, nw, ix->n_wg, s));
-  FR_HIP(hipEventRecord(w.e_scan1, s));
+  if (timing) FR_HIP(hipEventRecord(w.e_scan1, s));
 
   SelectArgs se{};
   se.qlist = w.qlist;
@@ -477,8 +473,28 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_q
     rs.out_nmatch = o_nmatch;
     FR_HIP(launch_rescore(rs, s));
   }
-  FR_HIP(hipEventRecord(w.e_end, s));
+  if (timing) FR_HIP(hipEventRecord(w.e_end, s));
   return FR_OK;
+}
+
+// Pick the timing-ring slot of a call and remember it in the history.
+void ring_slot(fr_index* ix, Workspace& w) {
+  const int slot = (int)(w.n_calls % Workspace::kRing);
+  w.e_scan0 = w.r0[slot];
+  w.e_scan1 = w.r1[slot];
+  w.e_end = w.r2[slot];
+  w.n_calls += 1;
+  ix->history.emplace_back((uint32_t)(&w - ix->ws.data()), (uint32_t)slot);
+  if (ix->history.size() > (size_t)Workspace::kRing)
+    ix->history.erase(ix->history.begin(),
+                      ix->history.begin() + (ix->history.size() - Workspace::kRing));
+}
+
+void drop_graph(Workspace& w) {
+  if (w.gexec) (void)hipGraphExecDestroy(w.gexec);
+  if (w.graph) (void)hipGraphDestroy(w.graph);
+  w.gexec = nullptr;
+  w.graph = nullptr;
 }
 
 fr_status validate_cnf(const fr_index* ix, uint32_t n_q, const fr_cnf_batch* cnf, uint32_t* n_c,
@@ -652,7 +668,7 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(dalloc(&w.qlist2, qm, D));
     FR_ALLOC(dalloc(&w.ovf, qm, D));
     FR_ALLOC(dalloc(&w.sel_cnt, qm, D));
-    FR_ALLOC(dalloc(&w.lit, (size_t)qm * 16, D));
+    FR_ALLOC(dalloc(&w.lit, (size_t)qm * kLits, D));
     FR_ALLOC(dalloc(&w.linfo, qm, D));
     FR_ALLOC(dalloc(&w.desc, 4, D));
     FR_ALLOC(dalloc(&w.work, kXcds, D));
@@ -719,6 +735,7 @@ fr_status fr_destroy(fr_index* ix) {
         (void)hipEventSynchronize(w.done);
         (void)hipEventDestroy(w.done);
       }
+      drop_graph(w);
       for (int i = 0; i < Workspace::kRing; ++i) {
         if (w.r0[i]) (void)hipEventDestroy(w.r0[i]);
         if (w.r1[i]) (void)hipEventDestroy(w.r1[i]);
@@ -916,8 +933,38 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   float* o_scores = dev ? out_scores : w->out_scores;
   uint32_t* o_count = dev ? out_count : w->out_count;
   unsigned long long* o_nm = dev ? (unsigned long long*)out_nmatch : w->out_nmatch;
-  st = enqueue_search(ix, *w, s, n_q, o_ids, o_scores, o_count, o_nm);
-  if (st != FR_OK) return st;
+  int qb = 1, nw = 4;
+  pick_tiling(ix, n_q, &qb, &nw);
+  const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
+  const int gpi = pick_gpi(ix, n_q, 32 * qb * nw, n_groups);
+  ring_slot(ix, *w);
+  if (flags & FR_GRAPH) {
+    // the whole device sequence as one graph, captured once per tiling,
+    // corpus extent and output binding; kernels read the batch size from the
+    // workspace descriptor, so any batch reuses the graph
+    const uint64_t key[8] = {(uint64_t)qb, (uint64_t)nw, (uint64_t)gpi, n_groups,
+                             (uint64_t)(uintptr_t)o_ids, (uint64_t)(uintptr_t)o_scores,
+                             (uint64_t)(uintptr_t)o_count, (uint64_t)(uintptr_t)o_nm};
+    if (!w->gexec || std::memcmp(key, w->gkey, sizeof key) != 0) {
+      drop_graph(*w);
+      FR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      st = enqueue_search(ix, *w, s, qb, nw, gpi, n_groups, false, o_ids, o_scores, o_count, o_nm);
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(s, &g);
+      if (st != FR_OK) return st;
+      FR_HIP(ce);
+      w->graph = g;
+      FR_HIP(hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0));
+      std::memcpy(w->gkey, key, sizeof key);
+    }
+    FR_HIP(hipEventRecord(w->e_scan0, s));
+    FR_HIP(hipGraphLaunch(w->gexec, s));
+    FR_HIP(hipEventRecord(w->e_scan1, s));
+    FR_HIP(hipEventRecord(w->e_end, s));
+  } else {
+    st = enqueue_search(ix, *w, s, qb, nw, gpi, n_groups, true, o_ids, o_scores, o_count, o_nm);
+    if (st != FR_OK) return st;
+  }
   const size_t kk = (size_t)n_q * ix->cfg.k_max;
   if (!dev) {
     FR_HIP(hipMemcpyAsync(w->h_ids, w->out_ids, kk * 4, hipMemcpyDeviceToHost, s));
@@ -1171,11 +1218,13 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
       if (!scan_supported(ix->dt, ix->dpad, qb, nw)) continue;
       const uint32_t qt = 32u * qb * nw;
       if (qt > round_up(std::max<uint32_t>(n_q, 1), 128) && qt > 128) continue;
+      ix->gpi = 0;
+      const int auto_g = pick_gpi(ix, n_q, (int)qt, n_groups);
       for (int g : {0, 1, 2, 4, 8}) {
+        if (g && g == auto_g) continue;   // same as the per-batch default
         ix->qb = qb;
         ix->nw = nw;
         ix->gpi = g;
-        if (g && g == pick_gpi(ix, n_q, (int)qt, n_groups)) continue;
         float tot = 0;
         for (int rep = 0; rep < 3; ++rep) {
           fr_status st = fr_search(ix, n_q, queries, cnf, k, ids.data(), sc.data(), cnt.data(),

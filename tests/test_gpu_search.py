@@ -118,6 +118,29 @@ def test_edge_cases():
     ix.close()
 
 
+def test_long_predicates_take_the_general_mask_path(tiny):
+    """Queries with more literals than the scan's literal table holds (12)
+    are evaluated from the CSR arrays; both paths must agree with the
+    oracle bit for bit."""
+    c, qb, o = tiny
+    ix = gpu_index(c, k_max=10)
+    rng = np.random.default_rng(11)
+    cnfs = []
+    for n_lit in (11, 12, 13, 16, 24):
+        terms = rng.choice(c.cfg.vocab, size=n_lit, replace=False).tolist()
+        # three clauses: one big OR and two narrower ones
+        cut = [n_lit // 3, 2 * n_lit // 3]
+        cnfs.append([terms[:cut[0]] + [0, 1, 2], terms[cut[0]:cut[1]] + [3, 4],
+                     terms[cut[1]:] + [5]])
+    q = qb.emb[:len(cnfs)]
+    batch = datagen.from_cnf_lists(q, cnfs, [10] * len(cnfs))
+    words = ix.debug_masks(batch)
+    res = ix.search(q, batch, 10)
+    for i, cnf in enumerate(cnfs):
+        assert np.array_equal(masks_as_bytes(words[i], c.n), o.match_bitmap(cnf)), i
+        check_query(o, batch, i, res, 10)
+
+
 def test_duplicate_rows_break_ties_by_id():
     from paper_2402_13435_amd import Index
     rng = np.random.default_rng(3)
@@ -315,3 +338,20 @@ def test_device_pointers_and_stream(tiny):
     assert np.array_equal(out.ids.cpu().numpy().view(np.uint32), host.ids)
     assert np.array_equal(out.scores.cpu().numpy(), host.scores)
     assert np.array_equal(out.n_match.cpu().numpy().astype(np.uint64), host.n_match)
+
+
+def test_graph_replays_match_eager(mid):
+    """The captured search graph replayed several times, with eager searches
+    and different batch sizes in between, gives the eager result each time."""
+    c, qb, o = mid
+    ix = gpu_index(c, k_max=100, max_batch=256)
+    eager = ix.search(qb.emb, qb, 100)
+    sub = qb.subset(list(range(40)))
+    for rep in range(4):
+        g = ix.search(qb.emb, qb, 100, graph=True)
+        assert np.array_equal(g.ids, eager.ids) and np.array_equal(g.scores, eager.scores)
+        assert np.array_equal(g.n_match, eager.n_match) and np.array_equal(g.count, eager.count)
+        small = ix.search(sub.emb, sub, 100, graph=True)
+        assert np.array_equal(small.ids, eager.ids[:40])
+        e2 = ix.search(sub.emb, sub, 100)
+        assert np.array_equal(e2.ids, eager.ids[:40])
