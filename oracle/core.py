@@ -50,8 +50,10 @@ class OracleIndex:
         self.emb = np.zeros((0, dim), dtype=np.float32)
         self.ids = np.zeros(0, dtype=np.uint32)
         self.live = np.zeros(0, dtype=bool)
-        self.term_lists: List[np.ndarray] = []
-        self.row_of: Dict[int, int] = {}
+        # term sets as CSR: row r holds terms[off[r]:off[r+1]] (sorted, distinct)
+        self.off = np.zeros(1, dtype=np.int64)
+        self.terms = np.zeros(0, dtype=np.int64)
+        self._row_of: Optional[Dict[int, int]] = None
         self._postings: Optional[List[np.ndarray]] = None
 
     # ------------------------------------------------------------------ state
@@ -63,10 +65,35 @@ class OracleIndex:
     def n_live(self) -> int:
         return int(self.live.sum())
 
+    @staticmethod
+    def _csr_sets(n: int, term_off, terms):
+        """Per-row distinct sorted term sets of a CSR list (duplicates dropped)."""
+        term_off = np.asarray(term_off, dtype=np.int64)
+        terms = np.asarray(terms, dtype=np.int64)[term_off[0]:term_off[n]] if n else \
+            np.zeros(0, dtype=np.int64)
+        lens = np.diff(term_off[:n + 1])
+        rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+        key = rows * (int(terms.max()) + 1 if len(terms) else 1) + terms
+        if len(key) > 1 and not np.all(key[1:] > key[:-1]):
+            key = np.unique(key)                      # sort within rows, drop duplicates
+        width = int(terms.max()) + 1 if len(terms) else 1
+        rows = key // width
+        off = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(np.bincount(rows, minlength=n), out=off[1:])
+        return off, key - rows * width
+
+    @property
+    def row_of(self) -> Dict[int, int]:
+        if self._row_of is None:
+            self._row_of = {int(x): i for i, x in enumerate(self.ids)}
+        return self._row_of
+
+    def term_set(self, r: int) -> np.ndarray:
+        return self.terms[self.off[r]:self.off[r + 1]]
+
     def load(self, emb, ids, term_off, terms) -> None:
         emb = np.ascontiguousarray(emb, dtype=np.float32)
         ids = np.asarray(ids, dtype=np.uint32)
-        term_off = np.asarray(term_off, dtype=np.int64)
         terms = np.asarray(terms, dtype=np.uint32)
         if emb.shape != (len(ids), self.dim):
             raise ValueError("embedding shape")
@@ -77,9 +104,8 @@ class OracleIndex:
         self.emb = emb.copy()
         self.ids = ids.copy()
         self.live = np.ones(len(ids), dtype=bool)
-        self.term_lists = [np.unique(terms[term_off[i]:term_off[i + 1]])
-                           for i in range(len(ids))]
-        self.row_of = {int(x): i for i, x in enumerate(ids)}
+        self.off, self.terms = self._csr_sets(len(ids), term_off, terms)
+        self._row_of = None
         self._postings = None
 
     def update(self, del_ids, ins_ids, ins_emb, ins_term_off, ins_terms) -> None:
@@ -103,25 +129,25 @@ class OracleIndex:
             self.live[self.row_of[x]] = False
         if ins_ids:
             ins_emb = np.ascontiguousarray(ins_emb, dtype=np.float32).reshape(-1, self.dim)
-            off = np.asarray(ins_term_off, dtype=np.int64)
             base = self.n_rows
             self.emb = np.concatenate([self.emb, ins_emb])
             self.ids = np.concatenate([self.ids, np.asarray(ins_ids, dtype=np.uint32)])
             self.live = np.concatenate([self.live, np.ones(len(ins_ids), dtype=bool)])
+            off, terms = self._csr_sets(len(ins_ids), ins_term_off, ins_terms)
+            self.terms = np.concatenate([self.terms, terms])
+            self.off = np.concatenate([self.off, self.off[-1] + off[1:]])
+            rmap = self.row_of
             for j, x in enumerate(ins_ids):
-                self.term_lists.append(np.unique(np.asarray(
-                    ins_terms[off[j]:off[j + 1]], dtype=np.uint32)))
-                self.row_of[x] = base + j
+                rmap[x] = base + j
         self._postings = None
 
     # --------------------------------------------------------------- F-TBR
     def _posting_lists(self) -> List[np.ndarray]:
         """term -> sorted rows holding it (the transpose of the term lists)."""
         if self._postings is None:
-            lens = np.array([len(t) for t in self.term_lists], dtype=np.int64)
+            lens = np.diff(self.off)
             rows = np.repeat(np.arange(self.n_rows, dtype=np.int64), lens)
-            flat = (np.concatenate(self.term_lists) if self.n_rows
-                    else np.zeros(0, dtype=np.uint32)).astype(np.int64)
+            flat = self.terms
             order = np.argsort(flat, kind="stable")
             bounds = np.searchsorted(flat[order], np.arange(self.vocab + 1))
             srt = rows[order]

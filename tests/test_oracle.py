@@ -192,7 +192,7 @@ def test_updates_equal_rebuild():
         ix.update(u.del_ids, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
     # rebuild from the surviving rows
     keep = np.flatnonzero(ix.live)
-    lists = [ix.term_lists[r] for r in keep]
+    lists = [ix.term_set(r) for r in keep]
     off = np.cumsum([0] + [len(x) for x in lists])
     fresh = OracleIndex(cfg.dim, cfg.vocab)
     fresh.load(ix.emb[keep], ix.ids[keep], off, np.concatenate(lists))
