@@ -90,6 +90,223 @@ def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None):
             "res": res, "tiling": tiling}
 
 
+def stratified(qb, n: int):
+    """n queries spread over the batch's target selectivities."""
+    order = np.argsort(np.nan_to_num(qb.target_sel, nan=0.0), kind="stable")
+    idx = np.linspace(0, qb.n - 1, min(n, qb.n)).round().astype(int)
+    return sorted(set(int(order[i]) for i in idx))
+
+
+def oracle_sample(c, qb, sample, k_of):
+    from oracle import OracleIndex
+    o = OracleIndex(c.cfg.dim, c.cfg.vocab)
+    o.load(c.emb, c.ids, c.term_off, c.terms)
+    o._posting_lists()
+    t0 = time.perf_counter()
+    res = {q: o.search_one(qb.emb[q], qb.cnf(q), int(k_of(q))) for q in sample}
+    dt = time.perf_counter() - t0
+    return o, res, dt
+
+
+def precision_report(o, qb, res, ids, scores, counts, k_of):
+    """recall@K against the exact oracle and max |returned - exact| score."""
+    from oracle import recall_at_k
+    got, want, err = [], [], 0.0
+    for q, a in res.items():
+        cnt = int(counts[q])
+        g = ids[q, :cnt]
+        got.append(g.tolist())
+        want.append(a.ids.tolist())
+        if cnt:
+            err = max(err, float(np.abs(scores[q, :cnt].astype(np.float64) -
+                                        o.score_ids(qb.emb[q], g)).max()))
+    rec, skipped = recall_at_k(got, want)
+    return {"recall": round(rec, 5), "queries": len(got) - skipped, "max_score_err": err}
+
+
+def timed_search(torch, ix, qb, k, steps, warmup, graph=False):
+    from paper_2402_13435_amd import SearchResult
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(qb.emb).to(dev)
+    n_q = qb.n
+    out = SearchResult(torch.empty((n_q, ix.k_max), dtype=torch.int32, device=dev),
+                       torch.empty((n_q, ix.k_max), dtype=torch.float32, device=dev),
+                       torch.empty(n_q, dtype=torch.int32, device=dev),
+                       torch.empty(n_q, dtype=torch.int64, device=dev))
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ix.search(q, qb, k, out=out, stream=stream, graph=graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ix.search(q, qb, k, out=out, stream=stream, graph=graph)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    scan_ms, total_ms = ix.timings(steps)
+    st = ix.stats()
+    return {"elapsed": el, "qps": n_q * steps / el, "scan_ms": float(np.mean(scan_ms)),
+            "total_ms": float(np.mean(total_ms)), "stats": st,
+            "ids": out.ids.cpu().numpy().view(np.uint32), "scores": out.scores.cpu().numpy(),
+            "count": out.count.cpu().numpy().view(np.uint32)}
+
+
+def bench_precision(args, torch):
+    """10M x 256 corpus: BF16 and FP8 (first pass) + FP32 rescoring of R=4096
+    candidates vs the plain FP32 path on the same data; recall@100 and max
+    score error against the FP64 oracle on a stratified query sample."""
+    import datagen
+    from paper_2402_13435_amd import Index
+    cfg = datagen.CONFIGS["precision"]
+    if args.n_docs:
+        cfg = datagen.scaled(cfg, args.n_docs)
+    log(f"generating the precision workload ({cfg.n_docs} docs x {cfg.dim})")
+    c = datagen.corpus(cfg)
+    qb = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms))
+    k = 100
+    sample = stratified(qb, args.sample)
+    log(f"oracle on {len(sample)} stratified queries")
+    o, res, cpu_s = oracle_sample(c, qb, sample, lambda q: k)
+    forms = {}
+    for dt, r in (("f32", 0), ("bf16", 4096), ("fp8", 4096)):
+        log(f"{dt} index")
+        ix = Index(c.n, cfg.dim, cfg.vocab, k, dtype=dt, rescore_r=r, max_batch=qb.n)
+        ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
+        til = ix.autotune(qb.emb, qb, k)
+        t = timed_search(torch, ix, qb, k, args.steps, args.warmup)
+        st = t["stats"]
+        peak = {"f32": PEAKS["f32"], "bf16": PEAKS["bf16"], "fp8": PEAKS["fp8"]}[dt]
+        tf = 2.0 * cfg.dim * qb.n * st.n_live / (t["scan_ms"] * 1e-3) / 1e12
+        f = {"qps": round(t["qps"], 1), "scan_ms": round(t["scan_ms"], 3),
+             "search_ms_device": round(t["total_ms"], 3), "tiling": list(til),
+             "mfma_tflops": round(tf, 1), "mfma_frac": round(tf / peak, 4),
+             "hbm_gbs_alg": round(st.alg_bytes / (t["total_ms"] * 1e-3) / 1e9, 1),
+             "candidates_per_query": round(st.candidates / qb.n, 1), "rescore_r": r}
+        f.update(precision_report(o, qb, res, t["ids"], t["scores"], t["count"], lambda q: k))
+        forms[dt] = f
+        ix.close()
+    for dt in ("bf16", "fp8"):
+        forms[dt]["vs_f32_qps"] = round(forms[dt]["qps"] / forms["f32"]["qps"], 3)
+    line = {"metric": "filtered top-K QPS, BF16/FP8 vs FP32 at recall@100", "config": {
+        "workload": f"precision: {c.n:,} docs x {cfg.dim}-d, vocab {cfg.vocab}, {qb.n} queries "
+                    f"at 1%-50% selectivity, K=100, R=4096", "n_docs": c.n},
+        "forms": forms, "cpu_oracle_s_per_query": round(cpu_s / len(sample), 3),
+        "data": "synthetic"}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_batching(args, torch):
+    """10M x 128 BF16 corpus, vocab 16,384, 4,096 queries with K in
+    {10, 100, 1000}; the whole search replayed as one captured HIP graph with
+    the autotuned tiling."""
+    import datagen
+    from paper_2402_13435_amd import Index
+    cfg = datagen.CONFIGS["batching"]
+    if args.n_docs:
+        cfg = datagen.scaled(cfg, args.n_docs)
+    log(f"generating the batching workload ({cfg.n_docs} docs)")
+    c = datagen.corpus(cfg)
+    qb = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms))
+    sample = stratified(qb, args.sample)
+    log(f"oracle on {len(sample)} stratified queries")
+    o, res, cpu_s = oracle_sample(c, qb, sample, lambda q: qb.k[q])
+    ix = Index(c.n, cfg.dim, cfg.vocab, 1000, dtype="bf16", rescore_r=4096, rescore_min=1024,
+               max_batch=qb.n)
+    ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
+    til = ix.autotune(qb.emb, qb, qb.k)
+    t = timed_search(torch, ix, qb, qb.k, args.steps, args.warmup, graph=True)
+    eager = timed_search(torch, ix, qb, qb.k, max(2, args.steps // 4), 1, graph=False)
+    st = t["stats"]
+    tf = 2.0 * cfg.dim * qb.n * st.n_live / (eager["scan_ms"] * 1e-3) / 1e12
+    line = {"metric": "filtered top-K QPS (batched, hipGraph)", "config": {
+        "workload": f"batching: {c.n:,} docs x {cfg.dim}-d BF16, vocab {cfg.vocab}, {qb.n} queries, "
+                    "K in {10,100,1000}, selectivity 1e-5..0.5", "n_docs": c.n},
+        "qps_graph": round(t["qps"], 1), "qps_eager": round(eager["qps"], 1),
+        "search_ms_device": round(t["total_ms"], 3), "scan_ms": round(eager["scan_ms"], 3),
+        "tiling": list(til), "mfma_tflops": round(tf, 1), "mfma_frac": round(tf / PEAKS["bf16"], 4),
+        "candidates_per_query": round(st.candidates / qb.n, 1),
+        "data": "synthetic"}
+    line.update(precision_report(o, qb, res, t["ids"], t["scores"], t["count"],
+                                 lambda q: qb.k[q]))
+    ix.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_serving(args, torch):
+    """Resident BF16 corpus, Poisson arrivals at fixed rates, continuous
+    batching over several workspaces, document inserts and deletes at 1% of
+    the corpus per minute in 100 ms batches; p50/p99 latency and QPS."""
+    import threading
+    import datagen
+    from paper_2402_13435_amd import Index
+    from paper_2402_13435_amd.serve import Server, latency_summary
+    cfg = datagen.CONFIGS["serving"]
+    if args.n_docs:
+        cfg = datagen.scaled(cfg, args.n_docs)
+    log(f"generating the serving workload ({cfg.n_docs} docs)")
+    c = datagen.corpus(cfg)
+    qb = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms))
+    slots, bmax = 3, 256
+    ix = Index(int(c.n * 1.02) + 1024, cfg.dim, cfg.vocab, 100, dtype="bf16", rescore_r=1024,
+               max_batch=bmax, n_workspaces=slots)
+    ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
+    # saturation: back-to-back full batches
+    sub = qb.subset(list(range(bmax)))
+    t = timed_search(torch, ix, sub, sub.k, 5, 2)
+    sat = t["qps"]
+    per_min = 0.01 * c.n
+    upd_batch = max(2, int(per_min / 600))          # 100 ms batches
+    levels = []
+    for frac in args.levels:
+        rate = frac * sat
+        n_req = int(min(args.max_requests, max(200, rate * args.level_s)))
+        arr = datagen.arrivals(cfg, rate, n_req, level=len(levels))
+        srv = Server(ix, slots=slots, max_batch=bmax)
+        log_live = list(map(int, c.ids[:: max(1, c.n // 100000)]))
+        ups = datagen.update_log(cfg, np.asarray(log_live, dtype=np.uint32),
+                                 int(arr[-1] / 0.1) + 1, upd_batch)
+        stop = threading.Event()
+        applied = [0]
+
+        def updater():
+            for u in ups:
+                if stop.wait(0.1):
+                    return
+                srv.update(u.del_ids, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
+                applied[0] += 1
+
+        th = threading.Thread(target=updater, daemon=True)
+        futs = []
+        t0 = time.perf_counter()
+        th.start()
+        for i in range(n_req):
+            now = time.perf_counter() - t0
+            if arr[i] > now:
+                time.sleep(arr[i] - now)
+            qi = i % qb.n
+            futs.append(srv.submit(qb.emb[qi], qb.cnf(qi), int(qb.k[qi])))
+        reps = [f.result(timeout=120) for f in futs]
+        wall = time.perf_counter() - t0
+        stop.set()
+        th.join()
+        srv.close()
+        s = latency_summary(reps)
+        levels.append({"offered_qps": round(rate, 1), "achieved_qps": round(n_req / wall, 1),
+                       "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
+                       "requests": n_req, "mean_batch": round(float(np.mean(srv.batches)), 1),
+                       "update_batches": applied[0]})
+        log(json.dumps(levels[-1]))
+    line = {"metric": "serving: p50/p99 latency and QPS under Poisson arrivals", "config": {
+        "workload": f"serving: {c.n:,} docs x {cfg.dim}-d BF16 resident, vocab {cfg.vocab}, "
+                    f"K in {{10,100}}, updates 1%/min in 100 ms batches, {slots} workspaces, "
+                    f"batches <= {bmax}", "n_docs": c.n},
+        "saturation_qps": round(sat, 1), "levels": levels, "data": "synthetic"}
+    ix.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +315,17 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--config", default="fp32",
+                    choices=["fp32", "precision", "batching", "serving"],
+                    help="workload (default fp32: the benchmark line)")
+    ap.add_argument("--n-docs", type=int, default=0, help="resize the corpus (non-default configs)")
+    ap.add_argument("--sample", type=int, default=32, help="oracle-checked queries")
+    ap.add_argument("--levels", type=float, nargs="*", default=[0.1, 0.3, 0.5, 0.7, 0.9])
+    ap.add_argument("--level-s", type=float, default=10.0)
+    ap.add_argument("--max-requests", type=int, default=20000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, copy 1 GiB device buffers (a plain copy "
+                         "kernel of known size, to scale HBM counter readings)")
     ap.add_argument("--tiling", default="",
                     help="query_blocks,waves,groups_per_item for the FP32 path (default: autotune)")
     args = ap.parse_args()
@@ -112,6 +340,12 @@ def main() -> int:
         print("no GPU visible", file=sys.stderr)
         return 1
     torch.cuda.init()
+    if args.config == "precision":
+        return bench_precision(args, torch)
+    if args.config == "batching":
+        return bench_batching(args, torch)
+    if args.config == "serving":
+        return bench_serving(args, torch)
     log("generating the fp32 workload (1M docs x 128, 256 queries)")
     c, qb = datagen.workload("fp32")
     k = 100
@@ -154,6 +388,15 @@ def main() -> int:
         "tiling": {"query_blocks": f32["tiling"][0], "waves": f32["tiling"][1],
                    "groups_per_item": f32["tiling"][2]},
     }
+    if args.copy_calibration:
+        n = 1 << 28                                    # 1 GiB of float32
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n, "launches": 3}
+        del src, dst
     oracle_res = {}
     if not args.no_cpu:
         log("CPU oracle baseline")

@@ -106,6 +106,7 @@ struct RerunArgs {
   uint32_t* ovf;
   uint32_t* qlist2;
   uint32_t* n_list2;
+  const uint32_t* kp;
   uint32_t* tau;
   uint32_t* cnt;
   uint32_t* smax;
@@ -118,7 +119,6 @@ struct RerunArgs {
 struct ScanArgs {
   const uint8_t* tiles;
   const float* xscale;     // FP8 row scales or null
-  const uint32_t* slot_ids;
   const uint64_t* live;
   const uint64_t* bits;
   uint32_t vocab;
@@ -134,8 +134,7 @@ struct ScanArgs {
   uint32_t* hist;
   const float* hlo;
   const float* hinvw;
-  unsigned long long* cand_key;
-  uint32_t* cand_slot;
+  unsigned long long* cand_key;  // [q][cap]: score key << 32 | slot
   uint32_t cap;
   unsigned long long* nmatch;
   uint32_t* work;
@@ -156,10 +155,10 @@ struct SelectArgs {
   const uint32_t* kp;
   const uint32_t* tau;
   const uint32_t* cnt;
-  const unsigned long long* cand_key;
-  const uint32_t* cand_slot;
+  const unsigned long long* cand_key;   // score key << 32 | slot
+  const uint32_t* slot_ids;            // slot -> external id
   uint32_t cap;
-  unsigned long long* sel_key;   // [q][rmax]
+  unsigned long long* sel_key;   // [q][rmax]: score key << 32 | ~id
   uint32_t* sel_slot;
   uint32_t* sel_cnt;
   uint32_t rmax;

@@ -411,6 +411,34 @@ __global__ __launch_bounds__(256) void k_rerun(RerunArgs a) {
   a.ovf[q] = 0u;
   const uint32_t p = atomicAdd(a.n_list2, 1u);
   a.qlist2[p] = q;
+  // Raise the threshold from the complete first-pass histogram: the scan's
+  // own refreshes may have seen only part of it.  Same bucket rule (and
+  // one-bucket margin) as the scan's refresh.
+  uint32_t* h = a.hist + (uint64_t)q * kHist;
+  {
+    const uint32_t kp = a.kp[q];
+    const float lo0 = a.hlo[q], iw0 = a.hinvw[q];
+    uint32_t suffix = 0;
+    int bstar = -1;
+    for (int c = kNBC - 1; c >= 0 && bstar < 0; --c) {
+      if (suffix + h[c] < kp) {
+        suffix += h[c];
+        continue;
+      }
+      for (int f = 15; f >= 0; --f) {
+        suffix += h[kNBC + c * 16 + f];
+        if (suffix >= kp) {
+          bstar = c * 16 + f;
+          break;
+        }
+      }
+      if (bstar < 0) bstar = c * 16;   // coarse and fine counts disagree: stay safe
+    }
+    if (kp && bstar >= 2 && iw0 > 0.f) {
+      const uint32_t nk = fkey(lo0 + (float)(bstar - 1) / iw0);
+      if (nk > a.tau[q]) a.tau[q] = nk;
+    }
+  }
   const float lo = fmaxf(key2f(a.tau[q]), 0.f);
   const float hi = key2f(a.smax[q]);
   const float span = (hi - lo) * 1.0001f;
@@ -418,7 +446,6 @@ __global__ __launch_bounds__(256) void k_rerun(RerunArgs a) {
   a.hinvw[q] = (span > 0.f && isfinite(span)) ? (float)kNBF / span : 0.f;
   a.cnt[q] = 0u;
   a.smax[q] = 0u;
-  uint32_t* h = a.hist + (uint64_t)q * kHist;
   for (int i = 0; i < kHist; ++i) h[i] = 0u;
 }
 hipError_t launch_rerun(const RerunArgs& a, hipStream_t s) {
@@ -426,6 +453,7 @@ hipError_t launch_rerun(const RerunArgs& a, hipStream_t s) {
   FR_REQUIRE(a.ovf);
   FR_REQUIRE(a.qlist2);
   FR_REQUIRE(a.n_list2);
+  FR_REQUIRE(a.kp);
   FR_REQUIRE(a.tau);
   FR_REQUIRE(a.cnt);
   FR_REQUIRE(a.smax);
@@ -584,6 +612,22 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
   __shared__ uint64_t s_mask[QT * MS];
   __shared__ uint32_t s_lit[QT * kLits];
   __shared__ uint32_t s_item;
+  // Candidate staging, per wavefront: survivors are appended to LDS with
+  // LDS atomics; a flush reserves global space once per query (one global
+  // atomic per query per flush instead of one per lane and tile) and scatters
+  // the entries.  Entries are (score key << 32 | slot) plus the query's local
+  // index in the wavefront.
+  constexpr int SC = QB >= 4 ? 512 : 1024;   // staged entries per wavefront
+  constexpr int NQW = 32 * QB;               // queries per wavefront
+  __shared__ unsigned long long s_st_key[NW][SC];
+  __shared__ uint8_t s_st_q[NW][SC];
+  __shared__ uint32_t s_st_n[NW];
+  __shared__ uint32_t s_q_cnt[NW][NQW];      // count, then scatter cursor
+  __shared__ uint32_t s_q_base[NW][NQW];
+  __shared__ uint32_t s_q_glob[NW][NQW];
+  __shared__ uint32_t s_q_max[NW][NQW];
+  __shared__ float s_q_lo[NW][NQW];
+  __shared__ float s_q_iw[NW][NQW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5,
             col = lane & 31;
@@ -607,9 +651,70 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
   int rstage = 0, rb = 0, rnext = 0;
   uint32_t rdirty = 0, rsuffix = 0, rcut = 0;
   uint32_t rr[16];  // coarse counts (stage 1), then fine counts (stage 2)
+  int warm = 0;     // active tiles since the queries were loaded
   uint32_t dirty[QB];
 #pragma unroll
   for (int b = 0; b < QB; ++b) dirty[b] = 0u;
+  if (lane == 0) s_st_n[wave] = 0u;
+  for (int j = lane; j < NQW; j += 64) {
+    s_q_cnt[wave][j] = 0u;
+    s_q_max[wave][j] = 0u;
+  }
+  auto wave_sync = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  // Flush this wavefront's staged candidates to the global buffers.
+  auto flush = [&]() {
+    wave_sync();
+    uint32_t n = s_st_n[wave];
+    if (n == 0u) return;
+    n = n < (uint32_t)SC ? n : (uint32_t)SC;
+    for (uint32_t i = lane; i < n; i += 64) atomicAdd(&s_q_cnt[wave][s_st_q[wave][i]], 1u);
+    wave_sync();
+#pragma unroll
+    for (int jj = 0; jj < (NQW + 63) / 64; ++jj) {
+      const int j = lane + 64 * jj;
+      uint32_t c = 0;
+      if (j < NQW) {
+        c = s_q_cnt[wave][j];
+        if (c) s_q_base[wave][j] = atomicAdd(a.cnt + s_q_glob[wave][j], c);
+        s_q_cnt[wave][j] = 0u;
+      }
+      const uint64_t bal = __ballot(c != 0u);
+#pragma unroll
+      for (int b = 0; b < QB; ++b) {
+        if (b == 2 * jj) dirty[b] |= (uint32_t)bal;
+        if (b == 2 * jj + 1) dirty[b] |= (uint32_t)(bal >> 32);
+      }
+    }
+    wave_sync();
+    for (uint32_t i = lane; i < n; i += 64) {
+      const uint32_t j = s_st_q[wave][i];
+      const unsigned long long key = s_st_key[wave][i];
+      const uint32_t r = atomicAdd(&s_q_cnt[wave][j], 1u);
+      const uint32_t pos = s_q_base[wave][j] + r;
+      const uint32_t qg = s_q_glob[wave][j];
+      if (pos < a.cap) a.cand_key[(uint64_t)qg * a.cap + pos] = key;
+      const uint32_t k32 = (uint32_t)(key >> 32);
+      const float fb = (key2f(k32) - s_q_lo[wave][j]) * s_q_iw[wave][j];
+      const int bk = fb >= (float)(kNBF - 1) ? kNBF - 1 : (fb > 0.f ? (int)fb : 0);
+      uint32_t* hq = a.hist + (uint64_t)qg * kHist;
+      atomicAdd(hq + kNBC + bk, 1u);
+      atomicAdd(hq + (bk >> 4), 1u);
+      atomicMax(&s_q_max[wave][j], k32);
+    }
+    wave_sync();
+    for (int j = lane; j < NQW; j += 64) {
+      const uint32_t m = s_q_max[wave][j];
+      if (m) atomicMax(a.smax + s_q_glob[wave][j], m);
+      s_q_max[wave][j] = 0u;
+      s_q_cnt[wave][j] = 0u;
+    }
+    if (lane == 0) s_st_n[wave] = 0u;
+    wave_sync();
+  };
 
   auto my_pos = [&](uint32_t qt, int b) -> uint32_t {
     return qt * QT + (uint32_t)((wave * QB + b) * 32 + col);
@@ -686,6 +791,11 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
       hinv[b] = qv[b] ? a.hinvw[q] : 0.f;
       qs[b] = (DT == kFP8 && qv[b]) ? a.qscale[q] : 1.f;
       thr[b] = -INFINITY;
+      if (half == 0) {
+        s_q_glob[wave][b * 32 + col] = q;
+        s_q_lo[wave][b * 32 + col] = hlo[b];
+        s_q_iw[wave][b * 32 + col] = hinv[b];
+      }
       const uint4* p = (const uint4*)(a.qtiles + (uint64_t)(q / kTile) * (CH * 1024)) +
                        half * 32 + (q % kTile);
 #pragma unroll
@@ -785,6 +895,7 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
     const uint64_t g1 = min(g0 + a.gpi, (uint64_t)a.n_groups);
 
     if (qt != cur_qt) {
+      flush();
       refresh_drain();
 #pragma unroll
       for (int b = 0; b < QB; ++b) dirty[b] = 0u;
@@ -793,6 +904,7 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
       load_queries(qt);
       load_jobs(qt);
       pending_g = ~0ull;
+      warm = 0;
     }
     if (pending_g != g0) {
 #pragma unroll 1
@@ -882,36 +994,55 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
                 if (((m32 >> acc_row(v, half)) & 1u) && s[v] >= thr[b]) pm |= 1u << v;
             }
             if (pm) {
+              const uint32_t p0 = atomicAdd(&s_st_n[wave], (uint32_t)__popc(pm));
               const uint32_t q = qi[b];
-              const uint32_t base = atomicAdd(a.cnt + q, (uint32_t)__popc(pm));
-              uint32_t* hq = a.hist + (uint64_t)q * kHist;
-              uint32_t kmax = 0, r = 0;
+              uint32_t r = 0;
 #pragma unroll
               for (int v = 0; v < 16; ++v) {
                 if ((pm >> v) & 1u) {
                   const uint64_t slot = (tile0 + t) * kTile + acc_row(v, half);
                   const uint32_t k32 = fkey(s[v]);
-                  kmax = kmax > k32 ? kmax : k32;
-                  const uint32_t pos = base + r++;
-                  if (pos < a.cap) {
-                    const uint32_t id = a.slot_ids[slot];
-                    a.cand_key[(uint64_t)q * a.cap + pos] =
-                        ((unsigned long long)k32 << 32) | (unsigned long long)(0xFFFFFFFFu - id);
-                    a.cand_slot[(uint64_t)q * a.cap + pos] = (uint32_t)slot;
+                  // the id (for the tie order) is looked up by the selection
+                  const unsigned long long key =
+                      ((unsigned long long)k32 << 32) | (unsigned long long)slot;
+                  const uint32_t idx = p0 + r++;
+                  if (idx < (uint32_t)SC) {
+                    s_st_key[wave][idx] = key;
+                    s_st_q[wave][idx] = (uint8_t)(b * 32 + col);
+                  } else {
+                    // staging full: append directly
+                    const uint32_t pos = atomicAdd(a.cnt + q, 1u);
+                    if (pos < a.cap) a.cand_key[(uint64_t)q * a.cap + pos] = key;
+                    const float fb = (s[v] - hlo[b]) * hinv[b];
+                    const int bk = fb >= (float)(kNBF - 1) ? kNBF - 1 : (fb > 0.f ? (int)fb : 0);
+                    uint32_t* hq = a.hist + (uint64_t)q * kHist;
+                    atomicAdd(hq + kNBC + bk, 1u);
+                    atomicAdd(hq + (bk >> 4), 1u);
+                    atomicMax(a.smax + q, k32);
                   }
-                  const float fb = (s[v] - hlo[b]) * hinv[b];
-                  const int bk = fb >= (float)(kNBF - 1) ? kNBF - 1 : (fb > 0.f ? (int)fb : 0);
-                  atomicAdd(hq + kNBC + bk, 1u);
-                  atomicAdd(hq + (bk >> 4), 1u);
                 }
               }
-              atomicMax(a.smax + q, kmax);
             }
             const uint64_t bal = __ballot(pm != 0u);
             dirty[b] |= (uint32_t)bal | (uint32_t)(bal >> 32);
           }
         }
-        refresh_step();
+        // keep the staging from filling up: flush once half full
+        {
+          wave_sync();
+          if (s_st_n[wave] > (uint32_t)(SC / 2)) flush();
+        }
+        // The first tiles after the queries are loaded run before any
+        // threshold exists and append every match: refresh those thresholds
+        // at once; afterwards the refresh overlaps the following tiles.
+        if (warm < 2) {
+          ++warm;
+          flush();
+          if (rstage == 0) refresh_step();
+          refresh_drain();
+        } else {
+          refresh_step();
+        }
         return tn;
       };
 
@@ -923,6 +1054,7 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
         if (t >= 32) break;
         t = body(b1, b0, t);
       }
+      flush();
       // finish the next group's masks
       if (mw_fly >= 0) mask_finish_word();
       while (mw_next < kWords) {
@@ -932,6 +1064,7 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
       pending_g = has_next ? g + 1 : ~0ull;
     }
   }
+  flush();
   refresh_drain();
   if (cur_qt != 0xFFFFFFFFu) flush_counts();
 }
@@ -946,7 +1079,7 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
   X(kFP8, 64, 1, 4) X(kFP8, 64, 2, 4) X(kFP8, 64, 4, 4) \
   X(kFP8, 128, 1, 4) X(kFP8, 128, 2, 4) X(kFP8, 128, 4, 4) \
   X(kFP8, 192, 1, 4) X(kFP8, 192, 2, 4) X(kFP8, 256, 1, 4) X(kFP8, 256, 2, 4) \
-  X(kBF16, 64, 1, 8) X(kFP8, 64, 1, 8) X(kFP8, 128, 1, 8)
+  X(kBF16, 64, 1, 8) X(kFP8, 64, 1, 8)
 
 bool scan_supported(int dt, int dpad, int qb, int nw) {
 #define FR_SUP(D, P, Q, W) if (dt == D && dpad == P && qb == Q && nw == W) return true;
@@ -958,7 +1091,6 @@ bool scan_supported(int dt, int dpad, int qb, int nw) {
 hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int n_wg,
                        hipStream_t s) {
   FR_REQUIRE(a.tiles);
-  FR_REQUIRE(a.slot_ids);
   FR_REQUIRE(a.live);
   FR_REQUIRE(a.bits);
   FR_REQUIRE(a.qtiles);
@@ -972,7 +1104,6 @@ hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int 
   FR_REQUIRE(a.hlo);
   FR_REQUIRE(a.hinvw);
   FR_REQUIRE(a.cand_key);
-  FR_REQUIRE(a.cand_slot);
   FR_REQUIRE(a.nmatch);
   FR_REQUIRE(a.work);
   FR_REQUIRE(a.clause_off);
@@ -1060,16 +1191,21 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
   }
   const uint32_t tau = a.tau[q];
   const unsigned long long* ck = a.cand_key + (uint64_t)q * a.cap;
-  const uint32_t* cs = a.cand_slot + (uint64_t)q * a.cap;
+  // a candidate is stored as (score key, slot); its sort key is (score key,
+  // complement of the slot's id)
+  auto sort_key = [&](unsigned long long raw) -> unsigned long long {
+    const uint32_t id = a.slot_ids[(uint32_t)raw];
+    return (raw & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - id);
+  };
   if (threadIdx.x == 0) s_n = 0u;
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
-    const unsigned long long k = ck[i];
-    if ((uint32_t)(k >> 32) >= tau) {
+    const unsigned long long raw = ck[i];
+    if ((uint32_t)(raw >> 32) >= tau) {
       const uint32_t p = atomicAdd(&s_n, 1u);
       if (p < kSelCap) {
-        s_key[p] = k;
-        s_slot[p] = cs[i];
+        s_key[p] = sort_key(raw);
+        s_slot[p] = (uint32_t)raw;
       }
     }
   }
@@ -1083,9 +1219,10 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
       for (int i = threadIdx.x; i < 256; i += blockDim.x) s_hist[i] = 0u;
       __syncthreads();
       for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
-        const unsigned long long k = ck[i];
-        if ((uint32_t)(k >> 32) >= tau && (k & pmask) == prefix)
-          atomicAdd(&s_hist[(k >> shift) & 255u], 1u);
+        const unsigned long long raw = ck[i];
+        if ((uint32_t)(raw >> 32) < tau) continue;
+        const unsigned long long k = sort_key(raw);
+        if ((k & pmask) == prefix) atomicAdd(&s_hist[(k >> shift) & 255u], 1u);
       }
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -1106,12 +1243,14 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     if (threadIdx.x == 0) s_n = 0u;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
-      const unsigned long long k = ck[i];
-      if ((uint32_t)(k >> 32) >= tau && k >= kth) {
+      const unsigned long long raw = ck[i];
+      if ((uint32_t)(raw >> 32) < tau) continue;
+      const unsigned long long k = sort_key(raw);
+      if (k >= kth) {
         const uint32_t p = atomicAdd(&s_n, 1u);
         if (p < kSelCap) {
           s_key[p] = k;
-          s_slot[p] = cs[i];
+          s_slot[p] = (uint32_t)raw;
         }
       }
     }
@@ -1154,7 +1293,7 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
   FR_REQUIRE(a.tau);
   FR_REQUIRE(a.cnt);
   FR_REQUIRE(a.cand_key);
-  FR_REQUIRE(a.cand_slot);
+  FR_REQUIRE(a.slot_ids);
   FR_REQUIRE(a.sel_key);
   FR_REQUIRE(a.sel_slot);
   FR_REQUIRE(a.sel_cnt);

@@ -92,7 +92,6 @@ struct Workspace {
   float* hinvw = nullptr;
   unsigned long long* nmatch = nullptr;
   unsigned long long* cand_key = nullptr;
-  uint32_t* cand_slot = nullptr;
   unsigned long long* sel_key = nullptr;
   uint32_t* sel_slot = nullptr;
   uint32_t* out_ids = nullptr;
@@ -368,7 +367,6 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   ScanArgs sa{};
   sa.tiles = ix->tiles;
   sa.xscale = ix->xscale;
-  sa.slot_ids = ix->slot_ids;
   sa.live = ix->live;
   sa.bits = ix->bits;
   sa.vocab = ix->cfg.vocab;
@@ -385,7 +383,6 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sa.hlo = w.hlo;
   sa.hinvw = w.hinvw;
   sa.cand_key = w.cand_key;
-  sa.cand_slot = w.cand_slot;
   sa.cap = ix->cand_cap;
   sa.nmatch = w.nmatch;
   sa.work = w.work;
@@ -409,7 +406,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   se.tau = w.tau;
   se.cnt = w.cnt;
   se.cand_key = w.cand_key;
-  se.cand_slot = w.cand_slot;
+  se.slot_ids = ix->slot_ids;
   se.cap = ix->cand_cap;
   se.sel_key = w.sel_key;
   se.sel_slot = w.sel_slot;
@@ -433,6 +430,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   ra.ovf = w.ovf;
   ra.qlist2 = w.qlist2;
   ra.n_list2 = w.desc + 2;
+  ra.kp = w.kp;
   ra.tau = w.tau;
   ra.cnt = w.cnt;
   ra.smax = w.smax;
@@ -676,7 +674,6 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(dalloc(&w.hinvw, qm, D));
     FR_ALLOC(dalloc(&w.nmatch, qm, D));
     FR_ALLOC(dalloc(&w.cand_key, (size_t)qm * ix->cand_cap, D));
-    FR_ALLOC(dalloc(&w.cand_slot, (size_t)qm * ix->cand_cap, D));
     FR_ALLOC(dalloc(&w.sel_key, (size_t)qm * ix->rmax, D));
     FR_ALLOC(dalloc(&w.sel_slot, (size_t)qm * ix->rmax, D));
     FR_ALLOC(dalloc(&w.out_ids, (size_t)qm * cfg->k_max, D));
