@@ -475,77 +475,136 @@ hipError_t launch_zero_work(uint32_t* work, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- the scan
-template <int DT>
-struct Mma;
-
-template <>
-struct Mma<kF32> {
-  // 32x32x2 FP32: each 16-byte chunk holds 4 consecutive k values per lane.
-  template <int CH>
-  __device__ static __forceinline__ void run(f32x16& acc, const uint4 (&a)[CH],
-                                             const uint4 (&b)[CH]) {
+// Matrix-core products of one tile (A: 32 documents, from the LDS ring)
+// with QB blocks of 32 queries (B, in registers).  The k order inside a
+// 16-byte chunk is the same for both operands, so any fixed pairing of
+// chunks gives the dot products.  A chunks are read from LDS one at a time
+// and used for every query block before the next is read.
+template <int DT, int CH, int QB>
+__device__ __forceinline__ void mma_tile(f32x16 (&acc)[QB], const uint8_t* slot,
+                                         const uint4 (&bq)[QB][CH], int lane) {
+  const uint4* p = (const uint4*)slot + lane;
+  if constexpr (DT == kF32) {
+    // 32x32x2 FP32: a chunk holds 4 consecutive k values per lane
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[j].x), __uint_as_float(b[j].x), acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[j].y), __uint_as_float(b[j].y), acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[j].z), __uint_as_float(b[j].z), acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[j].w), __uint_as_float(b[j].w), acc, 0, 0, 0);
-    }
-  }
-};
-
-template <>
-struct Mma<kBF16> {
-  // 32x32x16 BF16: one chunk = the 8 k values of one instruction.
-  template <int CH>
-  __device__ static __forceinline__ void run(f32x16& acc, const uint4 (&a)[CH],
-                                             const uint4 (&b)[CH]) {
+      const uint4 x = p[j * 64];
 #pragma unroll
-    for (int j = 0; j < CH; ++j)
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[j]),
-                                                     __builtin_bit_cast(bf16x8, b[j]), acc, 0, 0, 0);
-  }
-};
-
-template <>
-struct Mma<kFP8> {
-  // 32x32x64 FP8 (E4M3, format code 0 for both operands, no block scale):
-  // two chunks = the 32 k values of one instruction.
-  template <int CH>
-  __device__ static __forceinline__ void run(f32x16& acc, const uint4 (&a)[CH],
-                                             const uint4 (&b)[CH]) {
+      for (int b = 0; b < QB; ++b) {
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x.x), __uint_as_float(bq[b][j].x), acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x.y), __uint_as_float(bq[b][j].y), acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x.z), __uint_as_float(bq[b][j].z), acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x.w), __uint_as_float(bq[b][j].w), acc[b], 0, 0, 0);
+      }
+    }
+  } else if constexpr (DT == kBF16) {
+    // 32x32x16 BF16: one chunk = the 8 k values of one instruction
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const uint4 x = p[j * 64];
+#pragma unroll
+      for (int b = 0; b < QB; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x),
+                                                          __builtin_bit_cast(bf16x8, bq[b][j]),
+                                                          acc[b], 0, 0, 0);
+    }
+  } else {
+    // 32x32x64 FP8 (E4M3, format code 0 for both operands, no block scale):
+    // two chunks = the 32 k values of one instruction
 #pragma unroll
     for (int j = 0; j < CH; j += 2) {
-      const i32x8 av = {(int)a[j].x, (int)a[j].y, (int)a[j].z, (int)a[j].w,
-                        (int)a[j + 1].x, (int)a[j + 1].y, (int)a[j + 1].z, (int)a[j + 1].w};
-      const i32x8 bv = {(int)b[j].x, (int)b[j].y, (int)b[j].z, (int)b[j].w,
-                        (int)b[j + 1].x, (int)b[j + 1].y, (int)b[j + 1].z, (int)b[j + 1].w};
-      acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 0, 0, 0);
+      const uint4 x0 = p[j * 64], x1 = p[(j + 1) * 64];
+      const i32x8 av = {(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w,
+                        (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+#pragma unroll
+      for (int b = 0; b < QB; ++b) {
+        const i32x8 bv = {(int)bq[b][j].x, (int)bq[b][j].y, (int)bq[b][j].z, (int)bq[b][j].w,
+                          (int)bq[b][j + 1].x, (int)bq[b][j + 1].y, (int)bq[b][j + 1].z,
+                          (int)bq[b][j + 1].w};
+        acc[b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[b], 0, 0, 0, 0, 0, 0);
+      }
     }
   }
-};
+}
 
 // Row (within the 32-row tile) of accumulator element v of a lane in half h.
 __device__ __forceinline__ int acc_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
-template <int DT, int CH>
-struct TileBuf {
-  uint4 a[CH];
-  float4 xs[4];  // FP8 row scales of the lane's 16 rows
+// Ring of corpus tiles in LDS.  One wavefront of the workgroup (the loader)
+// copies tiles straight from HBM into ring slots (global_load_lds, 16 bytes
+// per lane: one instruction moves one kilobyte chunk, which is exactly the
+// chunk-major tile layout); the compute wavefronts read them with plain LDS
+// loads.  Keeping the tile loads on their own wavefront keeps them out of
+// the compute wavefronts' memory counters, so candidate atomics and mask
+// loads there never wait behind tile traffic.
+template <int DT, int DPAD>
+struct Ring {
+  static constexpr int ES = DT == kF32 ? 4 : DT == kBF16 ? 2 : 1;
+  static constexpr int CH = DPAD * ES / 32;   // 1 KB chunks per tile
+  static constexpr int TB = CH * 1024;       // tile bytes
+  static constexpr int L = CH + (DT == kFP8 ? 1 : 0);   // loads per tile
+  // tiles in flight ahead of the one being scored: about 64 KB of ring,
+  // at least 2, at most 8, and within the 6-bit memory counter
+  static constexpr int PD0 = 65536 / TB - 1;
+  static constexpr int PD1 = PD0 < 2 ? 2 : PD0 > 8 ? 8 : PD0;
+  static constexpr int PD = (PD1 - 1) * L <= 63 ? PD1 : 63 / L + 1;
+  static constexpr int NS = PD + 1;          // slots
 };
 
+__device__ __forceinline__ constexpr int vm_wait_code(int n) {
+  // s_waitcnt with vmcnt(n) only (expcnt and lgkmcnt at their maximum)
+  return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00;
+}
+
+// Workgroup barrier for LDS hand-offs: this wavefront's LDS accesses are
+// complete before it arrives; memory accesses are not moved across it.
+__device__ __forceinline__ void wg_barrier() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+  __builtin_amdgcn_s_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
+
+// Copy tile `tile` (and its FP8 row scales) into one ring slot.
 template <int DT, int CH>
-__device__ __forceinline__ void load_tile(TileBuf<DT, CH>& t, const uint8_t* __restrict__ tiles,
-                                          const float* __restrict__ xscale, uint64_t tile,
-                                          int lane) {
-  const uint4* p = (const uint4*)(tiles + tile * (uint64_t)(CH * 1024)) + lane;
+__device__ __forceinline__ void dma_tile(const uint8_t* __restrict__ tiles,
+                                         const float* __restrict__ xscale, uint64_t tile,
+                                         uint8_t* slot, float* sslot, int lane) {
+  const uint4* src = (const uint4*)(tiles + tile * (uint64_t)(CH * 1024)) + lane;
 #pragma unroll
-  for (int j = 0; j < CH; ++j) t.a[j] = p[j * 64];
+  for (int j = 0; j < CH; ++j)
+    __builtin_amdgcn_global_load_lds((const void*)(src + j * 64),
+                                     (__attribute__((address_space(3))) void*)(slot + j * 1024),
+                                     16, 0, 0);
   if constexpr (DT == kFP8) {
-    const float4* s = (const float4*)(xscale + tile * kTile) + (lane >> 5);
-#pragma unroll
-    for (int g = 0; g < 4; ++g) t.xs[g] = s[2 * g];
+    if (lane < kTile)
+      __builtin_amdgcn_global_load_lds((const void*)(xscale + tile * kTile + lane),
+                                       (__attribute__((address_space(3))) void*)sslot, 4, 0, 0);
   }
+}
+
+// Wait until at most `younger` tiles' loads of this wavefront are in flight.
+template <int L, int PD>
+__device__ __forceinline__ void wait_tiles(uint32_t younger) {
+  static_assert((PD - 1) * L <= 63, "memory counter range");
+  switch (younger) {
+    case 0: __builtin_amdgcn_s_waitcnt(vm_wait_code(0)); break;
+    case 1: __builtin_amdgcn_s_waitcnt(vm_wait_code(1 * L)); break;
+    case 2: if constexpr (PD > 2) { __builtin_amdgcn_s_waitcnt(vm_wait_code(2 * L)); break; }
+    case 3: if constexpr (PD > 3) { __builtin_amdgcn_s_waitcnt(vm_wait_code(3 * L)); break; }
+    case 4: if constexpr (PD > 4) { __builtin_amdgcn_s_waitcnt(vm_wait_code(4 * L)); break; }
+    case 5: if constexpr (PD > 5) { __builtin_amdgcn_s_waitcnt(vm_wait_code(5 * L)); break; }
+    case 6: if constexpr (PD > 6) { __builtin_amdgcn_s_waitcnt(vm_wait_code(6 * L)); break; }
+    case 7: if constexpr (PD > 7) { __builtin_amdgcn_s_waitcnt(vm_wait_code(7 * L)); break; }
+    default: __builtin_amdgcn_s_waitcnt(vm_wait_code(0)); break;
+  }
+}
+
+// FP8 row scales of the lane's 16 accumulator rows from a ring slot
+__device__ __forceinline__ void read_scales(float4 (&xs)[4], const float* sslot, int lane) {
+  const float4* s = (const float4*)sslot + (lane >> 5);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) xs[g] = s[2 * g];
 }
 
 // Literal table of one query (built by the prep kernel): up to kLits term
@@ -587,13 +646,15 @@ __device__ __forceinline__ uint64_t mask_combine(const MaskJob& j, uint32_t info
   return m & cw;
 }
 
-// One pass of the fused scan.  A workgroup of NW wavefronts takes work
-// items (a chunk of 1024-document groups x a tile of NW*QB*32 queries) from
-// its XCD's queue; wavefront w owns QB blocks of 32 queries whose B operand
-// stays in registers.  With eight wavefronts (two per SIMD) one wavefront's
-// loads overlap the other's matrix work.  Per group, each wavefront:
-//   * reads its queries' masks for the group from LDS and skips 32-document
-//     tiles no query of it matches,
+// One pass of the fused scan.  A workgroup of NW compute wavefronts and one
+// loader wavefront takes work items (a chunk of 1024-document groups x a
+// tile of NW*QB*32 queries) from its XCD's queue.  The loader streams every
+// tile of the item's groups into the LDS ring, a few tiles ahead; one
+// workgroup barrier per tile hands a slot over.  Compute wavefront w owns QB
+// blocks of 32 queries whose B operand stays in registers.  Per group, each
+// compute wavefront:
+//   * reads its queries' masks for the group from LDS and skips the matrix
+//     work of 32-document tiles no query of it matches,
 //   * scores each remaining tile on the matrix cores (32 docs x 32 queries
 //     per instruction chain, FP32 accumulate),
 //   * drops (doc, query) pairs that fail the mask or score below the
@@ -603,12 +664,14 @@ __device__ __forceinline__ uint64_t mask_combine(const MaskJob& j, uint32_t info
 //     queries that received candidates in a three-step pipeline whose loads
 //     also overlap the matrix-core work.
 template <int DT, int DPAD, int QB, int NW>
-__global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
-  constexpr int ES = DT == kF32 ? 4 : DT == kBF16 ? 2 : 1;
-  constexpr int CH = DPAD * ES / 32;        // 16-byte chunks per lane per tile
+__global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
+  using R = Ring<DT, DPAD>;
+  constexpr int CH = R::CH;                 // 16-byte chunks per lane per tile
   constexpr int QT = NW * QB * 32;          // queries per work item
   constexpr int MS = kWords + 1;            // padded mask row (bank spread)
   constexpr int NJ = (QB + 1) / 2;          // mask-job queries per lane
+  __shared__ __attribute__((aligned(16))) uint8_t s_ring[R::NS * R::TB];
+  __shared__ __attribute__((aligned(16))) float s_rscale[DT == kFP8 ? R::NS * kTile : 4];
   __shared__ uint64_t s_mask[QT * MS];
   __shared__ uint32_t s_lit[QT * kLits];
   __shared__ uint32_t s_item;
@@ -617,7 +680,8 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
   // atomic per query per flush instead of one per lane and tile) and scatters
   // the entries.  Entries are (score key << 32 | slot) plus the query's local
   // index in the wavefront.
-  constexpr int SC = QB >= 4 ? 512 : 1024;   // staged entries per wavefront
+  constexpr int LDS_REST = R::NS * R::TB + QT * (MS * 8 + kLits * 4 + 24);
+  constexpr int SC = LDS_REST + NW * 1024 * 9 > 150 * 1024 ? 512 : 1024;   // staged entries per wavefront
   constexpr int NQW = 32 * QB;               // queries per wavefront
   __shared__ unsigned long long s_st_key[NW][SC];
   __shared__ uint8_t s_st_q[NW][SC];
@@ -637,6 +701,38 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
   const uint32_t n_chunks = (a.n_groups + a.gpi - 1) / a.gpi;
   const uint32_t my_chunks = n_chunks > xcd ? (n_chunks - xcd + kXcds - 1) / kXcds : 0u;
   const uint32_t my_items = my_chunks * n_qtiles;
+
+  if (wave == NW) {
+    // ---------------------------------------------------------- loader
+    // Same item sequence and barrier count as the compute wavefronts: two
+    // barriers per item fetch, one per tile.  Tile i of an item goes to
+    // slot i % NS; it is issued after barrier i - PD, when every compute
+    // wavefront is done with the slot's previous tile (i - NS = i - PD - 1).
+    for (;;) {
+      wg_barrier();
+      const uint32_t item = s_item;
+      wg_barrier();
+      if (item >= my_items) break;
+      const uint32_t chunk = (item / n_qtiles) * kXcds + xcd;
+      const uint64_t g0 = (uint64_t)chunk * a.gpi;
+      const uint64_t g1 = min(g0 + a.gpi, (uint64_t)a.n_groups);
+      const uint32_t n_t = (uint32_t)(g1 - g0) * (kGroup / kTile);
+      const uint64_t tile0 = g0 * (uint64_t)(kGroup / kTile);
+      for (uint32_t i = 0; i < (uint32_t)R::PD && i < n_t; ++i)
+        dma_tile<DT, CH>(a.tiles, a.xscale, tile0 + i, s_ring + (i % R::NS) * R::TB,
+                         s_rscale + (i % R::NS) * kTile, lane);
+      for (uint32_t i = 0; i < n_t; ++i) {
+        const uint32_t left = n_t - 1 - i;
+        wait_tiles<R::L, R::PD>(left < (uint32_t)(R::PD - 1) ? left : (uint32_t)(R::PD - 1));
+        wg_barrier();
+        const uint32_t nx = i + R::PD;
+        if (nx < n_t)
+          dma_tile<DT, CH>(a.tiles, a.xscale, tile0 + nx, s_ring + (nx % R::NS) * R::TB,
+                           s_rscale + (nx % R::NS) * kTile, lane);
+      }
+    }
+    return;
+  }
 
   // matrix-core B operand and per-query state, block b -> query column col
   uint4 bq[QB][CH];
@@ -885,9 +981,9 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
   uint64_t pending_g = ~0ull;   // group whose masks are already in LDS
   for (;;) {
     if (tid == 0) s_item = atomicAdd(a.work + xcd, 1u);
-    __syncthreads();
+    wg_barrier();
     const uint32_t item = s_item;
-    __syncthreads();
+    wg_barrier();
     if (item >= my_items) break;
     const uint32_t qt = item % n_qtiles;
     const uint32_t chunk = (item / n_qtiles) * kXcds + xcd;
@@ -960,23 +1056,30 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
         mw_fly = -1;
       };
 
-      auto body = [&](TileBuf<DT, CH>& cur, TileBuf<DT, CH>& nxt, int t) -> int {
-        const uint32_t rest = act & ~((2u << t) - 1u);
-        const int tn = rest ? __builtin_ctz(rest) : 32;
-        if (tn < 32) load_tile<DT, CH>(nxt, a.tiles, a.xscale, tile0 + tn, lane);
+      // one step per tile of the group: wait for the tile's ring slot, then
+      // (if a query of this wavefront matches the tile) score it
+      auto body = [&](int t, uint32_t rs) {
+        wg_barrier();
         // words whose current-group tiles are all behind us can be replaced
         if (mw_fly >= 0 && 2 * mw_fly + 1 < t) mask_finish_word();
         if (mw_fly < 0 && mw_next < kWords && mw_next <= (t >> 1) + 1) mask_issue_word(mw_next++);
+        if (!((act >> t) & 1u)) return;
+        f32x16 accs[QB];
+#pragma unroll
+        for (int b = 0; b < QB; ++b)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) accs[b][v] = 0.f;
+        mma_tile<DT, CH, QB>(accs, s_ring + rs * R::TB, bq, lane);
+        float4 xs[4];
+        if constexpr (DT == kFP8) read_scales(xs, s_rscale + rs * kTile, lane);
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
-          f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                        0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-          Mma<DT>::template run<CH>(acc, cur.a, bq[b]);
+          f32x16& acc = accs[b];
           const uint32_t m32 = (uint32_t)(smask(b, col, t >> 1) >> ((t & 1) * 32));
           if constexpr (DT == kFP8) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-              const float4 x4 = cur.xs[v >> 2];
+              const float4 x4 = xs[v >> 2];
               const float sc = (v & 3) == 0 ? x4.x : (v & 3) == 1 ? x4.y : (v & 3) == 2 ? x4.z : x4.w;
               acc[v] = (acc[v] * qs[b]) * sc;
             }
@@ -1043,17 +1146,11 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
         } else {
           refresh_step();
         }
-        return tn;
       };
 
-      TileBuf<DT, CH> b0, b1;
-      int t = act ? __builtin_ctz(act) : 32;
-      if (t < 32) load_tile<DT, CH>(b0, a.tiles, a.xscale, tile0 + t, lane);
-      while (t < 32) {
-        t = body(b0, b1, t);
-        if (t >= 32) break;
-        t = body(b1, b0, t);
-      }
+      const uint32_t ti0 = (uint32_t)(g - g0) * (kGroup / kTile);   // item-relative tile
+#pragma unroll 1
+      for (int t = 0; t < kGroup / kTile; ++t) body(t, (ti0 + (uint32_t)t) % (uint32_t)R::NS);
       flush();
       // finish the next group's masks
       if (mw_fly >= 0) mask_finish_word();
@@ -1071,15 +1168,10 @@ __global__ __launch_bounds__(NW * 64) void k_scan(ScanArgs a) {
 
 // (dtype, padded dim, query blocks per wavefront, wavefronts per workgroup)
 #define FR_SCAN_CASES(X) \
-  X(kF32, 64, 1, 4) X(kF32, 64, 2, 4) X(kF32, 128, 1, 4) X(kF32, 128, 2, 4) \
-  X(kF32, 192, 1, 4) X(kF32, 256, 1, 4) \
-  X(kBF16, 64, 1, 4) X(kBF16, 64, 2, 4) X(kBF16, 64, 4, 4) \
-  X(kBF16, 128, 1, 4) X(kBF16, 128, 2, 4) \
-  X(kBF16, 192, 1, 4) X(kBF16, 192, 2, 4) X(kBF16, 256, 1, 4) \
-  X(kFP8, 64, 1, 4) X(kFP8, 64, 2, 4) X(kFP8, 64, 4, 4) \
-  X(kFP8, 128, 1, 4) X(kFP8, 128, 2, 4) X(kFP8, 128, 4, 4) \
-  X(kFP8, 192, 1, 4) X(kFP8, 192, 2, 4) X(kFP8, 256, 1, 4) X(kFP8, 256, 2, 4) \
-  X(kBF16, 64, 1, 8) X(kFP8, 64, 1, 8)
+  X(kF32, 64, 1, 4) X(kF32, 128, 1, 4) X(kF32, 192, 1, 4) X(kF32, 256, 1, 4) \
+  X(kBF16, 64, 1, 4) X(kBF16, 128, 1, 4) X(kBF16, 192, 1, 4) X(kBF16, 256, 1, 4) \
+  X(kFP8, 64, 1, 4) X(kFP8, 64, 2, 4) X(kFP8, 128, 1, 4) X(kFP8, 128, 2, 4) \
+  X(kFP8, 192, 1, 4) X(kFP8, 256, 1, 4)
 
 bool scan_supported(int dt, int dpad, int qb, int nw) {
 #define FR_SUP(D, P, Q, W) if (dt == D && dpad == P && qb == Q && nw == W) return true;
@@ -1118,7 +1210,7 @@ hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int 
   if (a.gpi < 1 || n_wg < 1) return hipErrorInvalidValue;
 #define FR_LAUNCH(D, P, Q, W)                                                          \
   if (dt == D && dpad == P && qb == Q && nw == W) {                                    \
-    hipLaunchKernelGGL((k_scan<D, P, Q, W>), dim3(n_wg), dim3(W * 64), 0, s, a);       \
+    hipLaunchKernelGGL((k_scan<D, P, Q, W>), dim3(n_wg), dim3((W + 1) * 64), 0, s, a); \
     return hipGetLastError();                                                          \
   }
   FR_SCAN_CASES(FR_LAUNCH)

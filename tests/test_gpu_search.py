@@ -169,7 +169,7 @@ def test_determinism_and_batch_invariance(mid):
         r = ix.search(one.emb, one, 100)
         assert np.array_equal(r.ids[0], a.ids[q]) and np.array_equal(r.scores[0], a.scores[q])
         assert r.n_match[0] == a.n_match[q]
-    for qbk, nw, g in ((1, 4, 1), (2, 4, 2), (1, 4, 3)):
+    for qbk, nw, g in ((1, 4, 1), (1, 4, 2), (1, 4, 7)):
         ix.set_tiling(qbk, nw, g)
         t = ix.search(qb.emb, qb, 100)
         assert np.array_equal(t.ids, a.ids) and np.array_equal(t.scores, a.scores)
@@ -214,6 +214,12 @@ def test_precision_forms(mid, dt):
         want.append(a.ids.tolist())
     rec, _ = recall_at_k(got, want)
     assert rec >= 0.99, rec
+    if dt == "fp8":
+        # another query-block tiling and chunk size give the same answer
+        ix.set_tiling(2, 4, 3)
+        t = ix.search(qb.emb, qb, k)
+        assert np.array_equal(t.ids, res.ids) and np.array_equal(t.scores, res.scores)
+        ix.set_tiling(0, 0, 0)
     # first pass: approximate scores against the oracle's emulation
     cid, csc, ccnt = ix.debug_candidates(qb.n)
     for q in range(0, qb.n, 8):
