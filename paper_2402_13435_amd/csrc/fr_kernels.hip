@@ -646,52 +646,61 @@ __device__ __forceinline__ uint64_t mask_combine(const MaskJob& j, uint32_t info
   return m & cw;
 }
 
-// One pass of the fused scan.  A workgroup of NW compute wavefronts and one
-// loader wavefront takes work items (a chunk of 1024-document groups x a
-// tile of NW*QB*32 queries) from its XCD's queue.  The loader streams every
-// tile of the item's groups into the LDS ring, a few tiles ahead; one
-// workgroup barrier per tile hands a slot over.  Compute wavefront w owns QB
-// blocks of 32 queries whose B operand stays in registers.  Per group, each
-// compute wavefront:
-//   * reads its queries' masks for the group from LDS and skips the matrix
-//     work of 32-document tiles no query of it matches,
-//   * scores each remaining tile on the matrix cores (32 docs x 32 queries
-//     per instruction chain, FP32 accumulate),
-//   * drops (doc, query) pairs that fail the mask or score below the
-//     query's threshold, and appends the rest as candidates,
-//   * meanwhile evaluates the predicate masks of the next group for its own
-//     queries (loads issued a tile ahead), and refreshes the thresholds of
-//     queries that received candidates in a three-step pipeline whose loads
-//     also overlap the matrix-core work.
+// One pass of the fused scan.  A workgroup has NW compute wavefronts and
+// two helpers, and takes work items (a chunk of 1024-document groups x a
+// tile of NW*QB*32 queries) from its XCD's queue:
+//   * the loader wavefront streams every tile of the item's groups into the
+//     LDS ring, a few tiles ahead;
+//   * compute wavefront w owns QB blocks of 32 queries (B operand in
+//     registers).  Per tile it scores the tile on the matrix cores (unless
+//     no query of it matches the tile), drops (doc, query) pairs that fail
+//     the predicate mask or score below the query's threshold, and stages
+//     the rest in LDS.  It also evaluates the next group's predicate masks
+//     for its queries (loads issued a tile ahead);
+//   * the keeper wavefront moves staged candidates to the global per-query
+//     buffers and histograms every F tiles, and raises the thresholds from
+//     the global histograms (a three-stage pipeline, one stage per F tiles,
+//     so its loads have F tiles to arrive).  Compute wavefronts read the
+//     thresholds from LDS at every tile.
+// Compute wavefronts thus issue no global atomics and wait on no global
+// loads in the tile loop, except when a staging buffer is full (then they
+// append directly).  One workgroup barrier per tile hands over a ring slot
+// and a staging half; every wavefront executes the same barrier sequence:
+// two per item fetch, one after the item set-up, one per tile, one at the
+// item end.
 template <int DT, int DPAD, int QB, int NW>
-__global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
+__global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   using R = Ring<DT, DPAD>;
   constexpr int CH = R::CH;                 // 16-byte chunks per lane per tile
   constexpr int QT = NW * QB * 32;          // queries per work item
   constexpr int MS = kWords + 1;            // padded mask row (bank spread)
   constexpr int NJ = (QB + 1) / 2;          // mask-job queries per lane
+  constexpr int F = 2;                      // tiles per keeper cycle
+  constexpr int SCH = 256;                  // staged entries per wavefront and half
+  constexpr int RJ = QT / 64;               // queries per keeper lane
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  static_assert(QT <= 256, "staged query index is one byte");
+  static_assert((kGroup / kTile) % F == 0, "cycles tile a group");
   __shared__ __attribute__((aligned(16))) uint8_t s_ring[R::NS * R::TB];
   __shared__ __attribute__((aligned(16))) float s_rscale[DT == kFP8 ? R::NS * kTile : 4];
   __shared__ uint64_t s_mask[QT * MS];
   __shared__ uint32_t s_lit[QT * kLits];
   __shared__ uint32_t s_item;
-  // Candidate staging, per wavefront: survivors are appended to LDS with
-  // LDS atomics; a flush reserves global space once per query (one global
-  // atomic per query per flush instead of one per lane and tile) and scatters
-  // the entries.  Entries are (score key << 32 | slot) plus the query's local
-  // index in the wavefront.
-  constexpr int LDS_REST = R::NS * R::TB + QT * (MS * 8 + kLits * 4 + 24);
-  constexpr int SC = LDS_REST + NW * 1024 * 9 > 150 * 1024 ? 512 : 1024;   // staged entries per wavefront
-  constexpr int NQW = 32 * QB;               // queries per wavefront
-  __shared__ unsigned long long s_st_key[NW][SC];
-  __shared__ uint8_t s_st_q[NW][SC];
-  __shared__ uint32_t s_st_n[NW];
-  __shared__ uint32_t s_q_cnt[NW][NQW];      // count, then scatter cursor
-  __shared__ uint32_t s_q_base[NW][NQW];
-  __shared__ uint32_t s_q_glob[NW][NQW];
-  __shared__ uint32_t s_q_max[NW][NQW];
-  __shared__ float s_q_lo[NW][NQW];
-  __shared__ float s_q_iw[NW][NQW];
+  // per query of the item, index j = (wave * QB + b) * 32 + col
+  __shared__ float s_thr[QT];
+  __shared__ uint32_t s_qg[QT];             // batch query index, kNone if unused
+  __shared__ uint32_t s_qkp[QT];            // selection size
+  __shared__ float s_qlo[QT];
+  __shared__ float s_qiw[QT];
+  // staging: entries (score key << 32 | slot) and the query's j, by half
+  __shared__ unsigned long long s_sk[2][NW][SCH];
+  __shared__ uint8_t s_sq[2][NW][SCH];
+  __shared__ uint32_t s_sn[2][NW];
+  // keeper scratch
+  __shared__ uint32_t s_hcnt[QT];
+  __shared__ uint32_t s_hbase[QT];
+  __shared__ uint32_t s_hmax[QT];
+  __shared__ uint32_t s_dirty[QT / 32];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5,
             col = lane & 31;
@@ -701,39 +710,258 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
   const uint32_t n_chunks = (a.n_groups + a.gpi - 1) / a.gpi;
   const uint32_t my_chunks = n_chunks > xcd ? (n_chunks - xcd + kXcds - 1) / kXcds : 0u;
   const uint32_t my_items = my_chunks * n_qtiles;
+  // the item's groups and tile count (identical in every wavefront)
+  auto item_range = [&](uint32_t item, uint64_t& g0, uint64_t& g1) {
+    const uint32_t chunk = (item / n_qtiles) * kXcds + xcd;
+    g0 = (uint64_t)chunk * a.gpi;
+    g1 = min(g0 + a.gpi, (uint64_t)a.n_groups);
+  };
+  auto wave_sync = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
 
   if (wave == NW) {
     // ---------------------------------------------------------- loader
-    // Same item sequence and barrier count as the compute wavefronts: two
-    // barriers per item fetch, one per tile.  Tile i of an item goes to
-    // slot i % NS; it is issued after barrier i - PD, when every compute
-    // wavefront is done with the slot's previous tile (i - NS = i - PD - 1).
+    // Tile i of an item goes to slot i % NS; it is issued after tile
+    // barrier i - PD, when every compute wavefront is done with the slot's
+    // previous tile (i - NS = i - PD - 1).
     for (;;) {
       wg_barrier();
       const uint32_t item = s_item;
       wg_barrier();
       if (item >= my_items) break;
-      const uint32_t chunk = (item / n_qtiles) * kXcds + xcd;
-      const uint64_t g0 = (uint64_t)chunk * a.gpi;
-      const uint64_t g1 = min(g0 + a.gpi, (uint64_t)a.n_groups);
+      uint64_t g0, g1;
+      item_range(item, g0, g1);
       const uint32_t n_t = (uint32_t)(g1 - g0) * (kGroup / kTile);
       const uint64_t tile0 = g0 * (uint64_t)(kGroup / kTile);
       for (uint32_t i = 0; i < (uint32_t)R::PD && i < n_t; ++i)
         dma_tile<DT, CH>(a.tiles, a.xscale, tile0 + i, s_ring + (i % R::NS) * R::TB,
                          s_rscale + (i % R::NS) * kTile, lane);
+      wg_barrier();                                   // set-up
       for (uint32_t i = 0; i < n_t; ++i) {
         const uint32_t left = n_t - 1 - i;
         wait_tiles<R::L, R::PD>(left < (uint32_t)(R::PD - 1) ? left : (uint32_t)(R::PD - 1));
-        wg_barrier();
+        wg_barrier();                                 // tile i
         const uint32_t nx = i + R::PD;
         if (nx < n_t)
           dma_tile<DT, CH>(a.tiles, a.xscale, tile0 + nx, s_ring + (nx % R::NS) * R::TB,
                            s_rscale + (nx % R::NS) * kTile, lane);
       }
+      wg_barrier();                                   // item end
     }
     return;
   }
 
+  if (wave == NW + 1) {
+    // ---------------------------------------------------------- keeper
+    // Move the staged entries of one half to the global buffers: count per
+    // query, reserve space with one atomic per query, scatter, add the
+    // histogram buckets, raise the running maximum.
+    auto flush_half = [&](int h) {
+      uint32_t n[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t c = s_sn[h][w];
+        n[w] = c < (uint32_t)SCH ? c : (uint32_t)SCH;
+      }
+#pragma unroll
+      for (int w = 0; w < NW; ++w)
+        for (uint32_t i = lane; i < n[w]; i += 64) atomicAdd(&s_hcnt[s_sq[h][w][i]], 1u);
+      wave_sync();
+      for (int j = lane; j < QT; j += 64) {
+        const uint32_t c = s_hcnt[j];
+        if (c) {
+          s_hbase[j] = atomicAdd(a.cnt + s_qg[j], c);
+          atomicOr(&s_dirty[j >> 5], 1u << (j & 31));
+        }
+        s_hcnt[j] = 0u;
+      }
+      wave_sync();
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        for (uint32_t i = lane; i < n[w]; i += 64) {
+          const uint32_t j = s_sq[h][w][i];
+          const unsigned long long key = s_sk[h][w][i];
+          const uint32_t r = atomicAdd(&s_hcnt[j], 1u);
+          const uint32_t pos = s_hbase[j] + r;
+          const uint32_t qg = s_qg[j];
+          if (pos < a.cap) a.cand_key[(uint64_t)qg * a.cap + pos] = key;
+          const uint32_t k32 = (uint32_t)(key >> 32);
+          const float fb = (key2f(k32) - s_qlo[j]) * s_qiw[j];
+          const int bk = fb >= (float)(kNBF - 1) ? kNBF - 1 : (fb > 0.f ? (int)fb : 0);
+          uint32_t* hq = a.hist + (uint64_t)qg * kHist;
+          atomicAdd(hq + kNBC + bk, 1u);
+          atomicAdd(hq + (bk >> 4), 1u);
+          atomicMax(&s_hmax[j], k32);
+        }
+      }
+      wave_sync();
+      for (int j = lane; j < QT; j += 64) {
+        const uint32_t m = s_hmax[j];
+        if (m) atomicMax(a.smax + s_qg[j], m);
+        s_hmax[j] = 0u;
+        s_hcnt[j] = 0u;
+      }
+      if (lane < NW) s_sn[h][lane] = 0u;
+      wave_sync();
+    };
+
+    // Threshold pipeline; lane owns queries j = lane + 64 r.  rstage: 0 idle,
+    // 1 coarse counts in flight, 2 coarse counts used (fine counts to
+    // issue), 3 fine counts in flight.  A cycle first uses the loads issued
+    // one cycle earlier, then moves the staged entries, then issues the next
+    // loads: loads are used only after a whole cycle, and never wait behind
+    // the atomics issued in the same cycle.
+    int rstage = 0;
+    uint32_t rsel = 0;            // bit r: query j refreshed in this round
+    uint32_t rc[RJ][16];          // coarse, then fine counts
+    uint32_t rtau[RJ], rcut[RJ], rsuf[RJ];
+    auto refresh_issue = [&]() {
+      if (rstage == 0) {
+        rsel = 0;
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+          const int j = lane + 64 * r;
+          const uint32_t qg = s_qg[j];
+          const bool d = (s_dirty[j >> 5] >> (j & 31)) & 1u;
+          rtau[r] = qg != kNone ? ld_relaxed(a.tau + qg) : kKeyNegInf;
+          if (qg != kNone && d) rsel |= 1u << r;
+          const uint32_t* h = a.hist + (uint64_t)(qg != kNone ? qg : 0u) * kHist;
+#pragma unroll
+          for (int i = 0; i < kNBC; ++i) rc[r][i] = ((rsel >> r) & 1u) ? ld_relaxed(h + i) : 0u;
+        }
+        wave_sync();
+        for (int i = lane; i < QT / 32; i += 64) s_dirty[i] = 0u;
+        wave_sync();
+        rstage = 1;
+      } else if (rstage == 2) {
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+          const int j = lane + 64 * r;
+          const uint32_t qg = s_qg[j];
+          const bool me = rcut[r] != kNone;
+          const uint32_t* h = a.hist + (uint64_t)(qg != kNone ? qg : 0u) * kHist + kNBC +
+                              (me ? rcut[r] : 0u) * 16;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) rc[r][i] = me ? ld_relaxed(h + i) : 0u;
+        }
+        rstage = 3;
+      }
+    };
+    auto refresh_consume = [&]() {
+      if (rstage == 1) {
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+          const int j = lane + 64 * r;
+          const uint32_t qg = s_qg[j];
+          if (qg != kNone) {
+            const float t = key2f(rtau[r]);
+            if (t > s_thr[j]) s_thr[j] = t;
+          }
+          const uint32_t k = qg != kNone ? s_qkp[j] : 0u;
+          uint32_t suffix = 0, above = 0;
+          int cs = -1;
+#pragma unroll
+          for (int i = kNBC - 1; i >= 0; --i) {
+            const uint32_t ns = suffix + rc[r][i];
+            if (cs < 0 && ns >= k) { cs = i; above = suffix; }
+            suffix = ns;
+          }
+          const bool me = ((rsel >> r) & 1u) && k && cs >= 0;
+          rcut[r] = me ? (uint32_t)cs : kNone;
+          rsuf[r] = above;
+        }
+        rstage = 2;
+      } else if (rstage == 3) {
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+          const int j = lane + 64 * r;
+          if (rcut[r] == kNone) continue;
+          const uint32_t qg = s_qg[j];
+          const uint32_t k = s_qkp[j];
+          uint32_t suffix = rsuf[r];
+          int fs = -1;
+#pragma unroll
+          for (int i = 15; i >= 0; --i) {
+            const uint32_t ns = suffix + rc[r][i];
+            if (fs < 0 && ns >= k) fs = i;
+            suffix = ns;
+          }
+          const int bstar = (int)rcut[r] * 16 + (fs < 0 ? 0 : fs);
+          const float iw = s_qiw[j];
+          if (bstar >= 2 && iw > 0.f) {
+            const float t = s_qlo[j] + (float)(bstar - 1) / iw;
+            if (t > s_thr[j]) s_thr[j] = t;
+            // publish without waiting: other workgroups pick it up on their
+            // next reload
+            atomicMax(a.tau + qg, fkey(t));
+          }
+        }
+        rstage = 0;
+      }
+    };
+    // finish the round in flight (if any) at once
+    auto refresh_drain = [&]() {
+      while (rstage != 0) {
+        refresh_consume();
+        if (rstage == 2) refresh_issue();
+      }
+    };
+
+    for (;;) {
+      wg_barrier();
+      const uint32_t item = s_item;
+      wg_barrier();
+      if (item >= my_items) break;
+      uint64_t g0, g1;
+      item_range(item, g0, g1);
+      const uint32_t n_t = (uint32_t)(g1 - g0) * (kGroup / kTile);
+      wg_barrier();                                   // set-up: s_qg, s_thr valid
+      for (int i = lane; i < QT / 32; i += 64) s_dirty[i] = 0u;
+      for (int j = lane; j < QT; j += 64) {
+        s_hcnt[j] = 0u;
+        s_hmax[j] = 0u;
+      }
+      rstage = 0;
+      wave_sync();
+      for (uint32_t i = 0; i < n_t; ++i) {
+        wg_barrier();                                 // tile i
+        if (i % F == 0 && i > 0) {
+          // the previous cycle's half is complete.  While some query has no
+          // threshold yet (the first cycles of an item), run a whole
+          // refresh round at once: until then every match is a candidate.
+          refresh_consume();
+          flush_half((int)((i / F - 1) & 1u));
+          bool cold = false;
+          if (i <= 4 * F) {
+#pragma unroll
+            for (int r = 0; r < RJ; ++r) {
+              const int j = lane + 64 * r;
+              cold = cold || (s_qg[j] != kNone && s_thr[j] == -INFINITY);
+            }
+          }
+          if (__ballot(cold)) {
+            refresh_drain();
+            refresh_issue();
+            refresh_drain();
+          } else {
+            refresh_issue();
+          }
+        }
+      }
+      wg_barrier();                                   // item end
+      refresh_consume();
+      flush_half((int)((n_t / F - 1) & 1u));
+      if (rstage == 2) refresh_issue();
+      refresh_drain();
+    }
+    return;
+  }
+
+  // ------------------------------------------------------------ compute
+  constexpr int NQW = 32 * QB;              // queries per wavefront
   // matrix-core B operand and per-query state, block b -> query column col
   uint4 bq[QB][CH];
   uint32_t qi[QB], kp[QB];
@@ -743,78 +971,13 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
   // their literal terms live in s_lit
   uint32_t jinfo[NJ], jq[NJ], jcnt[NJ];
   bool jv[NJ];
-  // threshold refresh pipeline (wave-uniform stage / block / lane set)
-  int rstage = 0, rb = 0, rnext = 0;
-  uint32_t rdirty = 0, rsuffix = 0, rcut = 0;
-  uint32_t rr[16];  // coarse counts (stage 1), then fine counts (stage 2)
-  int warm = 0;     // active tiles since the queries were loaded
-  uint32_t dirty[QB];
-#pragma unroll
-  for (int b = 0; b < QB; ++b) dirty[b] = 0u;
-  if (lane == 0) s_st_n[wave] = 0u;
-  for (int j = lane; j < NQW; j += 64) {
-    s_q_cnt[wave][j] = 0u;
-    s_q_max[wave][j] = 0u;
-  }
-  auto wave_sync = [&]() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  };
-  // Flush this wavefront's staged candidates to the global buffers.
-  auto flush = [&]() {
-    wave_sync();
-    uint32_t n = s_st_n[wave];
-    if (n == 0u) return;
-    n = n < (uint32_t)SC ? n : (uint32_t)SC;
-    for (uint32_t i = lane; i < n; i += 64) atomicAdd(&s_q_cnt[wave][s_st_q[wave][i]], 1u);
-    wave_sync();
-#pragma unroll
-    for (int jj = 0; jj < (NQW + 63) / 64; ++jj) {
-      const int j = lane + 64 * jj;
-      uint32_t c = 0;
-      if (j < NQW) {
-        c = s_q_cnt[wave][j];
-        if (c) s_q_base[wave][j] = atomicAdd(a.cnt + s_q_glob[wave][j], c);
-        s_q_cnt[wave][j] = 0u;
-      }
-      const uint64_t bal = __ballot(c != 0u);
-#pragma unroll
-      for (int b = 0; b < QB; ++b) {
-        if (b == 2 * jj) dirty[b] |= (uint32_t)bal;
-        if (b == 2 * jj + 1) dirty[b] |= (uint32_t)(bal >> 32);
-      }
-    }
-    wave_sync();
-    for (uint32_t i = lane; i < n; i += 64) {
-      const uint32_t j = s_st_q[wave][i];
-      const unsigned long long key = s_st_key[wave][i];
-      const uint32_t r = atomicAdd(&s_q_cnt[wave][j], 1u);
-      const uint32_t pos = s_q_base[wave][j] + r;
-      const uint32_t qg = s_q_glob[wave][j];
-      if (pos < a.cap) a.cand_key[(uint64_t)qg * a.cap + pos] = key;
-      const uint32_t k32 = (uint32_t)(key >> 32);
-      const float fb = (key2f(k32) - s_q_lo[wave][j]) * s_q_iw[wave][j];
-      const int bk = fb >= (float)(kNBF - 1) ? kNBF - 1 : (fb > 0.f ? (int)fb : 0);
-      uint32_t* hq = a.hist + (uint64_t)qg * kHist;
-      atomicAdd(hq + kNBC + bk, 1u);
-      atomicAdd(hq + (bk >> 4), 1u);
-      atomicMax(&s_q_max[wave][j], k32);
-    }
-    wave_sync();
-    for (int j = lane; j < NQW; j += 64) {
-      const uint32_t m = s_q_max[wave][j];
-      if (m) atomicMax(a.smax + s_q_glob[wave][j], m);
-      s_q_max[wave][j] = 0u;
-      s_q_cnt[wave][j] = 0u;
-    }
-    if (lane == 0) s_st_n[wave] = 0u;
-    wave_sync();
-  };
+  if (wave == 0)
+    for (int i = lane; i < 2 * NW; i += 64) s_sn[i / NW][i % NW] = 0u;
 
   auto my_pos = [&](uint32_t qt, int b) -> uint32_t {
     return qt * QT + (uint32_t)((wave * QB + b) * 32 + col);
   };
+  auto my_j = [&](int b) -> int { return (wave * QB + b) * 32 + col; };
   auto smask = [&](int b, int c, int w) -> uint64_t& {
     return s_mask[((wave * QB + b) * 32 + c) * MS + w];
   };
@@ -847,7 +1010,6 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
     for (int j = 0; j < NJ; ++j)
       if (jv[j] && jcnt[j]) atomicAdd(a.nmatch + jq[j], (unsigned long long)jcnt[j]);
   };
-  // evaluate word w of group g for the lane's jobs, synchronously
   // evaluate words w and w+1 of group g for the lane's jobs (loads of both
   // words in flight together)
   auto masks_words_sync = [&](uint64_t g, int w) {
@@ -886,94 +1048,20 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
       hlo[b] = qv[b] ? a.hlo[q] : 0.f;
       hinv[b] = qv[b] ? a.hinvw[q] : 0.f;
       qs[b] = (DT == kFP8 && qv[b]) ? a.qscale[q] : 1.f;
-      thr[b] = -INFINITY;
+      thr[b] = (qv[b] && kp[b]) ? key2f(ld_relaxed(a.tau + q)) : INFINITY;
       if (half == 0) {
-        s_q_glob[wave][b * 32 + col] = q;
-        s_q_lo[wave][b * 32 + col] = hlo[b];
-        s_q_iw[wave][b * 32 + col] = hinv[b];
+        const int j = my_j(b);
+        s_qg[j] = (qv[b] && kp[b]) ? q : kNone;
+        s_qkp[j] = kp[b];
+        s_qlo[j] = hlo[b];
+        s_qiw[j] = hinv[b];
+        s_thr[j] = thr[b];
       }
       const uint4* p = (const uint4*)(a.qtiles + (uint64_t)(q / kTile) * (CH * 1024)) +
                        half * 32 + (q % kTile);
 #pragma unroll
       for (int j = 0; j < CH; ++j) bq[b][j] = qv[b] ? p[j * 64] : make_uint4(0, 0, 0, 0);
     }
-  };
-  // -- threshold refresh: coarse counts -> fine counts -> new threshold
-  auto refresh_step = [&]() {
-    if (rstage == 0) {
-      // pick the next block with dirty queries
-      int pick = -1;
-#pragma unroll
-      for (int i = 0; i < QB; ++i) {
-        const int b = (rnext + i) % QB;
-        if (pick < 0 && dirty[b]) pick = b;
-      }
-      if (pick < 0) return;
-      rb = pick;
-      rnext = (pick + 1) % QB;
-#pragma unroll
-      for (int b = 0; b < QB; ++b)
-        if (b == pick) { rdirty = dirty[b]; dirty[b] = 0u; }
-      const bool me = half == 0 && ((rdirty >> col) & 1u);
-      uint32_t q = 0;
-#pragma unroll
-      for (int b = 0; b < QB; ++b) if (b == rb) q = qi[b];
-      const uint32_t* h = a.hist + (uint64_t)q * kHist;
-#pragma unroll
-      for (int i = 0; i < kNBC; ++i) rr[i] = me ? ld_relaxed(h + i) : 0u;
-      rstage = 1;
-    } else if (rstage == 1) {
-      const bool me = half == 0 && ((rdirty >> col) & 1u);
-      uint32_t q = 0, k = 0;
-#pragma unroll
-      for (int b = 0; b < QB; ++b) if (b == rb) { q = qi[b]; k = kp[b]; }
-      uint32_t suffix = 0, above = 0;
-      int cs = -1;
-#pragma unroll
-      for (int i = kNBC - 1; i >= 0; --i) {
-        const uint32_t ns = suffix + rr[i];
-        if (cs < 0 && ns >= k) { cs = i; above = suffix; }
-        suffix = ns;
-      }
-      rcut = cs < 0 ? 0xFFFFFFFFu : (uint32_t)cs;
-      rsuffix = above;
-      const uint32_t* h = a.hist + (uint64_t)q * kHist + kNBC + (cs < 0 ? 0 : cs) * 16;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) rr[i] = (me && cs >= 0) ? ld_relaxed(h + i) : 0u;
-      rstage = 2;
-    } else {
-      const bool me = half == 0 && ((rdirty >> col) & 1u);
-      uint32_t q = 0, k = 0;
-      float lo = 0.f, iw = 0.f, cur = -INFINITY;
-#pragma unroll
-      for (int b = 0; b < QB; ++b)
-        if (b == rb) { q = qi[b]; k = kp[b]; lo = hlo[b]; iw = hinv[b]; cur = thr[b]; }
-      float nt = cur;
-      if (me && rcut != 0xFFFFFFFFu && k) {
-        uint32_t suffix = rsuffix;
-        int fs = -1;
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-          const uint32_t ns = suffix + rr[i];
-          if (fs < 0 && ns >= k) fs = i;
-          suffix = ns;
-        }
-        const int bstar = (int)rcut * 16 + (fs < 0 ? 0 : fs);
-        if (bstar >= 2 && iw > 0.f) {
-          const float t = lo + (float)(bstar - 1) / iw;
-          const uint32_t nk = fkey(t);
-          const uint32_t old = atomicMax(a.tau + q, nk);
-          nt = fmaxf(cur, key2f(old > nk ? old : nk));
-        }
-      }
-      nt = __shfl(nt, col);
-#pragma unroll
-      for (int b = 0; b < QB; ++b) if (b == rb) thr[b] = fmaxf(thr[b], nt);
-      rstage = 0;
-    }
-  };
-  auto refresh_drain = [&]() {
-    while (rstage != 0) refresh_step();
   };
 
   // ------------------------------------------------------------ items
@@ -986,34 +1074,24 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
     wg_barrier();
     if (item >= my_items) break;
     const uint32_t qt = item % n_qtiles;
-    const uint32_t chunk = (item / n_qtiles) * kXcds + xcd;
-    const uint64_t g0 = (uint64_t)chunk * a.gpi;
-    const uint64_t g1 = min(g0 + a.gpi, (uint64_t)a.n_groups);
+    uint64_t g0, g1;
+    item_range(item, g0, g1);
 
     if (qt != cur_qt) {
-      flush();
-      refresh_drain();
-#pragma unroll
-      for (int b = 0; b < QB; ++b) dirty[b] = 0u;
       if (cur_qt != 0xFFFFFFFFu) flush_counts();
       cur_qt = qt;
       load_queries(qt);
       load_jobs(qt);
       pending_g = ~0ull;
-      warm = 0;
     }
     if (pending_g != g0) {
 #pragma unroll 1
       for (int w = 0; w < kWords; w += 2) masks_words_sync(g0, w);
     }
+    wg_barrier();                                     // set-up
 
     for (uint64_t g = g0; g < g1; ++g) {
       const bool has_next = g + 1 < g1;
-      // thresholds may have been raised by other workgroups
-#pragma unroll
-      for (int b = 0; b < QB; ++b)
-        if (qv[b] && kp[b]) thr[b] = fmaxf(thr[b], key2f(ld_relaxed(a.tau + qi[b])));
-        else thr[b] = INFINITY;
       // tiles of this group that some query of this wavefront matches
       uint32_t act = 0;
 #pragma unroll 1
@@ -1027,7 +1105,7 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
       }
 
       const uint64_t tile0 = g * (uint64_t)(kGroup / kTile);
-      // next-group mask pipeline: word `mw_issue` has loads in flight
+      // next-group mask pipeline: word `mw_fly` has loads in flight
       int mw_next = has_next ? 0 : kWords;   // next word to issue
       int mw_fly = -1;                        // word in flight
       MaskJob mj[NJ];
@@ -1058,12 +1136,18 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
 
       // one step per tile of the group: wait for the tile's ring slot, then
       // (if a query of this wavefront matches the tile) score it
-      auto body = [&](int t, uint32_t rs) {
+      const uint32_t ti0 = (uint32_t)(g - g0) * (kGroup / kTile);   // item-relative tile
+      auto body = [&](int t) {
+        const uint32_t ti = ti0 + (uint32_t)t;
+        const uint32_t rs = ti % (uint32_t)R::NS;
+        const int h = (int)((ti / F) & 1u);
         wg_barrier();
         // words whose current-group tiles are all behind us can be replaced
         if (mw_fly >= 0 && 2 * mw_fly + 1 < t) mask_finish_word();
         if (mw_fly < 0 && mw_next < kWords && mw_next <= (t >> 1) + 1) mask_issue_word(mw_next++);
         if (!((act >> t) & 1u)) return;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) thr[b] = s_thr[my_j(b)];
         f32x16 accs[QB];
 #pragma unroll
         for (int b = 0; b < QB; ++b)
@@ -1097,8 +1181,9 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
                 if (((m32 >> acc_row(v, half)) & 1u) && s[v] >= thr[b]) pm |= 1u << v;
             }
             if (pm) {
-              const uint32_t p0 = atomicAdd(&s_st_n[wave], (uint32_t)__popc(pm));
+              const uint32_t p0 = atomicAdd(&s_sn[h][wave], (uint32_t)__popc(pm));
               const uint32_t q = qi[b];
+              const int jj = my_j(b);
               uint32_t r = 0;
 #pragma unroll
               for (int v = 0; v < 16; ++v) {
@@ -1109,9 +1194,9 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
                   const unsigned long long key =
                       ((unsigned long long)k32 << 32) | (unsigned long long)slot;
                   const uint32_t idx = p0 + r++;
-                  if (idx < (uint32_t)SC) {
-                    s_st_key[wave][idx] = key;
-                    s_st_q[wave][idx] = (uint8_t)(b * 32 + col);
+                  if (idx < (uint32_t)SCH) {
+                    s_sk[h][wave][idx] = key;
+                    s_sq[h][wave][idx] = (uint8_t)jj;
                   } else {
                     // staging full: append directly
                     const uint32_t pos = atomicAdd(a.cnt + q, 1u);
@@ -1122,36 +1207,17 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
                     atomicAdd(hq + kNBC + bk, 1u);
                     atomicAdd(hq + (bk >> 4), 1u);
                     atomicMax(a.smax + q, k32);
+                    atomicOr(&s_dirty[jj >> 5], 1u << (jj & 31));
                   }
                 }
               }
             }
-            const uint64_t bal = __ballot(pm != 0u);
-            dirty[b] |= (uint32_t)bal | (uint32_t)(bal >> 32);
           }
-        }
-        // keep the staging from filling up: flush once half full
-        {
-          wave_sync();
-          if (s_st_n[wave] > (uint32_t)(SC / 2)) flush();
-        }
-        // The first tiles after the queries are loaded run before any
-        // threshold exists and append every match: refresh those thresholds
-        // at once; afterwards the refresh overlaps the following tiles.
-        if (warm < 2) {
-          ++warm;
-          flush();
-          if (rstage == 0) refresh_step();
-          refresh_drain();
-        } else {
-          refresh_step();
         }
       };
 
-      const uint32_t ti0 = (uint32_t)(g - g0) * (kGroup / kTile);   // item-relative tile
 #pragma unroll 1
-      for (int t = 0; t < kGroup / kTile; ++t) body(t, (ti0 + (uint32_t)t) % (uint32_t)R::NS);
-      flush();
+      for (int t = 0; t < kGroup / kTile; ++t) body(t);
       // finish the next group's masks
       if (mw_fly >= 0) mask_finish_word();
       while (mw_next < kWords) {
@@ -1160,15 +1226,15 @@ __global__ __launch_bounds__((NW + 1) * 64) void k_scan(ScanArgs a) {
       }
       pending_g = has_next ? g + 1 : ~0ull;
     }
+    wg_barrier();                                     // item end
   }
-  flush();
-  refresh_drain();
   if (cur_qt != 0xFFFFFFFFu) flush_counts();
 }
 
 // (dtype, padded dim, query blocks per wavefront, wavefronts per workgroup)
 #define FR_SCAN_CASES(X) \
   X(kF32, 64, 1, 4) X(kF32, 128, 1, 4) X(kF32, 192, 1, 4) X(kF32, 256, 1, 4) \
+  X(kBF16, 64, 2, 4) \
   X(kBF16, 64, 1, 4) X(kBF16, 128, 1, 4) X(kBF16, 192, 1, 4) X(kBF16, 256, 1, 4) \
   X(kFP8, 64, 1, 4) X(kFP8, 64, 2, 4) X(kFP8, 128, 1, 4) X(kFP8, 128, 2, 4) \
   X(kFP8, 192, 1, 4) X(kFP8, 256, 1, 4)
@@ -1210,7 +1276,7 @@ hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int 
   if (a.gpi < 1 || n_wg < 1) return hipErrorInvalidValue;
 #define FR_LAUNCH(D, P, Q, W)                                                          \
   if (dt == D && dpad == P && qb == Q && nw == W) {                                    \
-    hipLaunchKernelGGL((k_scan<D, P, Q, W>), dim3(n_wg), dim3((W + 1) * 64), 0, s, a); \
+    hipLaunchKernelGGL((k_scan<D, P, Q, W>), dim3(n_wg), dim3((W + 2) * 64), 0, s, a); \
     return hipGetLastError();                                                          \
   }
   FR_SCAN_CASES(FR_LAUNCH)
