@@ -36,6 +36,28 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload: str, tiling) -> int | None:
+    """HBM bytes per scan launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the scan source or the
+    tiling differ from the ones the counters were taken with."""
+    import glob
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2402_13435_amd", "csrc", "fr_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*hbm_traffic*.md")):
+        with open(path) as f:
+            m = re.search(r"<!-- traffic: (\{.*\}) -->", f.read())
+        if not m:
+            continue
+        meta = json.loads(m.group(1))
+        if (meta.get("workload") == workload and meta.get("source_sha256") == sha and
+                list(meta.get("tiling", [])) == list(tiling)):
+            return int(meta["traffic_bytes"])
+    return None
+
+
 def cpu_baseline(c, qb, k: int, budget_s: float):
     """Time the FP64 oracle on the host over a bounded sample of queries."""
     from oracle import OracleIndex
@@ -324,8 +346,8 @@ def main() -> int:
     ap.add_argument("--level-s", type=float, default=10.0)
     ap.add_argument("--max-requests", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the timed region, copy 1 GiB device buffers (a plain copy "
-                         "kernel of known size, to scale HBM counter readings)")
+                    help="after the timed region, run an elementwise kernel that reads and "
+                         "writes 1 GiB (known traffic, to scale HBM counter readings)")
     ap.add_argument("--tiling", default="",
                     help="query_blocks,waves,groups_per_item for the FP32 path (default: autotune)")
     args = ap.parse_args()
@@ -378,7 +400,7 @@ def main() -> int:
         "roofline": {"bound": "mfma", "kernel": "k_scan",
                      "achieved": round(achieved_tf, 2), "peak": PEAKS["f32"],
                      "unit": "TFLOP/s", "frac": round(achieved_tf / PEAKS["f32"], 4),
-                     "traffic": None,
+                     "traffic": measured_traffic("fp32", f32["tiling"]),
                      "scan_ms": round(scan_avg_ms, 4),
                      "alg_flops_per_launch": flops,
                      "alg_bytes_per_launch": alg_bytes_scan,
@@ -393,7 +415,7 @@ def main() -> int:
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)     # one elementwise kernel: reads and writes 1 GiB
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n, "launches": 3}
         del src, dst
