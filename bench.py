@@ -279,23 +279,37 @@ def bench_serving(args, torch):
     sat = t["qps"]
     per_min = 0.01 * c.n
     upd_batch = max(2, int(per_min / 600))          # 100 ms batches
-    levels = []
+    # one update log for the whole run, applied in order across the levels
+    # (each batch deletes ids that are live once the batches before it ran)
+    plan = []
     for frac in args.levels:
         rate = frac * sat
         n_req = int(min(args.max_requests, max(200, rate * args.level_s)))
+        plan.append((rate, n_req))
+    n_upd = sum(int(n / r / 0.1) + 20 for r, n in plan)
+    log_live = np.asarray(c.ids[:: max(1, c.n // 100000)], dtype=np.uint32)
+    log(f"update log: {n_upd} batches of {upd_batch} documents")
+    ups = datagen.update_log(cfg, log_live, n_upd, upd_batch)
+    next_upd = [0]
+    upd_errors = []
+    levels = []
+    for rate, n_req in plan:
         arr = datagen.arrivals(cfg, rate, n_req, level=len(levels))
         srv = Server(ix, slots=slots, max_batch=bmax)
-        log_live = list(map(int, c.ids[:: max(1, c.n // 100000)]))
-        ups = datagen.update_log(cfg, np.asarray(log_live, dtype=np.uint32),
-                                 int(arr[-1] / 0.1) + 1, upd_batch)
         stop = threading.Event()
         applied = [0]
 
         def updater():
-            for u in ups:
+            while next_upd[0] < len(ups):
                 if stop.wait(0.1):
                     return
-                srv.update(u.del_ids, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
+                u = ups[next_upd[0]]
+                try:
+                    srv.update(u.del_ids, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
+                except Exception as e:   # reported in the output line
+                    upd_errors.append(repr(e))
+                    return
+                next_upd[0] += 1
                 applied[0] += 1
 
         th = threading.Thread(target=updater, daemon=True)
@@ -323,7 +337,8 @@ def bench_serving(args, torch):
         "workload": f"serving: {c.n:,} docs x {cfg.dim}-d BF16 resident, vocab {cfg.vocab}, "
                     f"K in {{10,100}}, updates 1%/min in 100 ms batches, {slots} workspaces, "
                     f"batches <= {bmax}", "n_docs": c.n},
-        "saturation_qps": round(sat, 1), "levels": levels, "data": "synthetic"}
+        "saturation_qps": round(sat, 1), "levels": levels, "update_errors": upd_errors,
+        "data": "synthetic"}
     ix.close()
     print(json.dumps(line), flush=True)
     return 0
