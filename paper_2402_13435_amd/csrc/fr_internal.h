@@ -116,6 +116,51 @@ struct RerunArgs {
   uint32_t* work;
 };
 
+// Predicate masks of one search pass, precomputed for the scan: word w of
+// group g for the query at position p of the pass's list is
+// mw[(g * kWords + w) * ppad + p].  Optionally adds each query's matches to
+// nmatch.
+struct MaskWordArgs {
+  const uint32_t* qlist;
+  const uint32_t* n_list;  // device: positions in the list
+  uint32_t max_list;       // grid size (positions)
+  uint32_t ppad;           // row stride of mw (>= positions, multiple of 256)
+  uint32_t n_groups;
+  uint32_t gpt;            // groups per thread
+  const uint64_t* live;
+  const uint64_t* bits;
+  uint32_t vocab;
+  const uint32_t* lit;     // per-query literal table (see PrepArgs)
+  const uint32_t* linfo;
+  const uint32_t* clause_off;
+  const uint32_t* literal_off;
+  const uint32_t* terms;
+  uint64_t* mw;
+  unsigned long long* nmatch;
+  uint32_t count_matches;
+};
+
+// Starting thresholds: for each query of the first pass, the K'-th best
+// score among the matches in the first few groups (less a rounding margin)
+// is a lower bound of its final K'-th best score.
+struct SeedArgs {
+  const uint32_t* qlist;
+  const uint32_t* n_list;  // device
+  uint32_t max_list;       // grid size (positions)
+  const uint32_t* kp;
+  const uint8_t* tiles;
+  const float* xscale;     // FP8 row scales or null
+  const uint8_t* qtiles;
+  const float* qscale;     // FP8 query scales or null
+  const float* qnorm;
+  const uint32_t* norm_max;
+  const uint64_t* mw;      // the pass's masks (see MaskWordArgs)
+  uint32_t ppad;
+  uint32_t n_groups;       // groups sampled
+  uint32_t dim;
+  uint32_t* tau;
+};
+
 struct ScanArgs {
   const uint8_t* tiles;
   const float* xscale;     // FP8 row scales or null
@@ -136,15 +181,10 @@ struct ScanArgs {
   const float* hinvw;
   unsigned long long* cand_key;  // [q][cap]: score key << 32 | slot
   uint32_t cap;
-  unsigned long long* nmatch;
   uint32_t* work;
   uint32_t gpi;            // groups per work item
-  uint32_t count_matches;
-  const uint32_t* clause_off;
-  const uint32_t* literal_off;
-  const uint32_t* terms;
-  const uint32_t* lit;     // per-query literal table (see PrepArgs)
-  const uint32_t* linfo;
+  const uint64_t* mw;      // predicate masks of the pass (see MaskWordArgs)
+  uint32_t ppad;
 };
 
 struct SelectArgs {
@@ -212,6 +252,8 @@ hipError_t launch_terms(const TermArgs& a, hipStream_t s);
 hipError_t launch_live(const LiveArgs& a, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_rerun(const RerunArgs& a, hipStream_t s);
+hipError_t launch_mask_words(const MaskWordArgs& a, hipStream_t s);
+hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s);
 hipError_t launch_zero_work(uint32_t* work, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int n_wg,
                        hipStream_t s);

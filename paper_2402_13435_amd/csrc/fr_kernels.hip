@@ -465,6 +465,245 @@ hipError_t launch_rerun(const RerunArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Predicate masks of a search pass (Sec. 5.3: a document passes when every
+// clause of the query's CNF has a term the document carries; with the live
+// bits ANDed in).  Eight lanes build the 16 words of one (query, group): lane
+// part p holds words 2p and 2p+1, so the live run and each literal's bitmap
+// run (128 bytes) are read by one coalesced 16-byte load per lane.  A thread
+// block covers 32 queries x gpt groups; the words are stored word-major so
+// that the scan reads one word of consecutive queries from consecutive
+// addresses.
+__global__ __launch_bounds__(256) void k_mask_words(MaskWordArgs a) {
+  const uint32_t part = threadIdx.x & 7u;
+  const uint32_t pos = blockIdx.x * 32u + (threadIdx.x >> 3);
+  const uint32_t n = *a.n_list;
+  if (pos >= n || pos >= a.max_list) return;
+  const uint32_t q = a.qlist[pos];
+  const uint32_t info = a.linfo[q];
+  const bool empty = (info >> 24) & 1u, has = (info >> 26) & 1u, slow = (info >> 25) & 1u;
+  const uint32_t nlit = info & 31u, starts = (info >> 8) & 0xFFFFu;
+  uint32_t tl[kLits];
+#pragma unroll
+  for (int i = 0; i < kLits; ++i) tl[i] = a.lit[(uint64_t)q * kLits + i];
+  const uint64_t g0 = (uint64_t)blockIdx.y * a.gpt;
+  const uint64_t g1 = min(g0 + a.gpt, (uint64_t)a.n_groups);
+  unsigned long long cnt = 0;
+  // words 2 part and 2 part + 1 of a 16-word run
+  auto run2 = [&](const uint64_t* run) -> uint4 { return ((const uint4*)run)[part]; };
+  for (uint64_t g = g0; g < g1; ++g) {
+    uint64_t m0 = 0ull, m1 = 0ull;
+    if (!empty) {
+      const uint4 v = run2(a.live + g * kWords);
+      m0 = ((uint64_t)v.y << 32) | v.x;
+      m1 = ((uint64_t)v.w << 32) | v.z;
+    }
+    if (!empty && has) {
+      const uint64_t* gb = a.bits + g * (uint64_t)a.vocab * kWords;
+      uint64_t c0 = 0ull, c1 = 0ull;
+      if (!slow) {
+        for (uint32_t i = 0; i < nlit; ++i) {
+          if (i > 0 && ((starts >> i) & 1u)) {
+            m0 &= c0;
+            m1 &= c1;
+            c0 = c1 = 0ull;
+          }
+          uint32_t t = tl[0];
+#pragma unroll
+          for (int k = 1; k < kLits; ++k) t = (uint32_t)k == i ? tl[k] : t;
+          const uint4 v = run2(gb + (uint64_t)t * kWords);
+          c0 |= ((uint64_t)v.y << 32) | v.x;
+          c1 |= ((uint64_t)v.w << 32) | v.z;
+        }
+        m0 &= c0;
+        m1 &= c1;
+      } else {
+        const uint32_t k0 = a.clause_off[q], k1 = a.clause_off[q + 1];
+        for (uint32_t c = k0; c < k1; ++c) {
+          c0 = c1 = 0ull;
+          for (uint32_t l = a.literal_off[c]; l < a.literal_off[c + 1]; ++l) {
+            const uint4 v = run2(gb + (uint64_t)a.terms[l] * kWords);
+            c0 |= ((uint64_t)v.y << 32) | v.x;
+            c1 |= ((uint64_t)v.w << 32) | v.z;
+          }
+          m0 &= c0;
+          m1 &= c1;
+        }
+      }
+    }
+    a.mw[(g * kWords + 2 * part) * a.ppad + pos] = m0;
+    a.mw[(g * kWords + 2 * part + 1) * a.ppad + pos] = m1;
+    cnt += (unsigned long long)(__popcll(m0) + __popcll(m1));
+  }
+  // the query's eight lanes are consecutive: sum their counts
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) cnt += __shfl_xor(cnt, o);
+  if (a.count_matches && part == 0 && cnt) atomicAdd(a.nmatch + q, cnt);
+}
+hipError_t launch_mask_words(const MaskWordArgs& a, hipStream_t s) {
+  FR_REQUIRE(a.qlist);
+  FR_REQUIRE(a.n_list);
+  FR_REQUIRE(a.live);
+  FR_REQUIRE(a.bits);
+  FR_REQUIRE(a.lit);
+  FR_REQUIRE(a.linfo);
+  FR_REQUIRE(a.clause_off);
+  FR_REQUIRE(a.literal_off);
+  FR_REQUIRE(a.terms);
+  FR_REQUIRE(a.mw);
+  FR_REQUIRE(a.nmatch);
+  if (a.gpt < 1 || a.ppad < a.max_list || a.ppad % 256u) return hipErrorInvalidValue;
+  if (a.max_list == 0 || a.n_groups == 0) return hipSuccess;
+  const dim3 grid((a.max_list + 31u) / 32u, (a.n_groups + a.gpt - 1u) / a.gpt);
+  hipLaunchKernelGGL(k_mask_words, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// E4M3 (FN) code -> value
+__device__ __forceinline__ float e4m3_to_f(uint32_t b) {
+  const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+  const float v = e == 0u ? (float)m * 0.001953125f                       // m / 8 * 2^-6
+                          : __uint_as_float(((e + 120u) << 23) | (m << 20));  // (1 + m/8) 2^(e-7)
+  return (b & 0x80u) ? -v : v;
+}
+
+// Starting thresholds from a sample (the first groups of the corpus).  One
+// wavefront per query: every lane scores one document of each 64-document
+// word (the tile layout pairs each document chunk with the query chunk that
+// holds the same dimensions), the scores of matching documents go to LDS,
+// and a most-significant-byte-first radix select finds the K'-th largest.
+// The scan accumulates in another order, so the threshold is lowered by
+// twice the FP32 summation bound gamma_d * |q| * max|x| (with 12.5 % slack
+// for the quantised forms' scaled norms): at least K' documents then score
+// at or above it in the scan, so it is a valid lower bound.
+template <int DT, int DPAD>
+__global__ __launch_bounds__(256) void k_seed(SeedArgs a) {
+  constexpr int ES = DT == kF32 ? 4 : DT == kBF16 ? 2 : 1;
+  constexpr int CH = DPAD * ES / 32;
+  constexpr int NS = 4 * kGroup;            // sampled documents at most
+  __shared__ uint32_t s_key[4][NS];
+  __shared__ uint32_t s_hist[4][256];
+  __shared__ uint32_t s_n[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t pos = blockIdx.x * 4u + (uint32_t)wave;
+  if (pos >= *a.n_list || pos >= a.max_list) return;
+  const uint32_t q = a.qlist[pos];
+  const uint32_t kp = a.kp[q];
+  const uint32_t ng = a.n_groups < 4u ? a.n_groups : 4u;
+  if (kp == 0u || kp > ng * (uint32_t)kGroup) return;
+  uint32_t* key = s_key[wave];
+  uint32_t* hist = s_hist[wave];
+  if (lane == 0) s_n[wave] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  const float qs = (DT == kFP8 && a.qscale) ? a.qscale[q] : 1.f;
+  const uint4* qt = (const uint4*)(a.qtiles + (uint64_t)(q / kTile) * (CH * 1024));
+  for (uint32_t g = 0; g < ng; ++g) {
+    for (int w = 0; w < kWords; ++w) {
+      const uint64_t m = a.mw[((uint64_t)g * kWords + w) * a.ppad + pos];
+      if (!m) continue;
+      const uint64_t slot = (uint64_t)g * kGroup + (uint64_t)w * 64 + lane;
+      const uint64_t tile = slot / kTile;
+      const uint32_t r = (uint32_t)(slot % kTile);
+      const uint4* xt = (const uint4*)(a.tiles + tile * (uint64_t)(CH * 1024));
+      float acc = 0.f;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll 4
+        for (int j = 0; j < CH; ++j) {
+          const uint4 x = xt[j * 64 + h * 32 + r];
+          const uint4 y = qt[j * 64 + h * 32 + (q % kTile)];
+          const uint32_t xv[4] = {x.x, x.y, x.z, x.w}, yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if constexpr (DT == kF32) {
+              acc = fmaf(__uint_as_float(xv[e]), __uint_as_float(yv[e]), acc);
+            } else if constexpr (DT == kBF16) {
+              acc = fmaf(__uint_as_float(xv[e] << 16), __uint_as_float(yv[e] << 16), acc);
+              acc = fmaf(__uint_as_float(xv[e] & 0xFFFF0000u), __uint_as_float(yv[e] & 0xFFFF0000u), acc);
+            } else {
+#pragma unroll
+              for (int b = 0; b < 4; ++b)
+                acc = fmaf(e4m3_to_f((xv[e] >> (8 * b)) & 0xFFu), e4m3_to_f((yv[e] >> (8 * b)) & 0xFFu), acc);
+            }
+          }
+        }
+      }
+      if constexpr (DT == kFP8) acc = (acc * qs) * a.xscale[slot];
+      if ((m >> lane) & 1ull) {
+        const uint32_t at = atomicAdd(&s_n[wave], 1u);
+        key[at] = fkey(acc);
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t n = s_n[wave];
+  if (n < kp) return;
+  // radix select of the kp-th largest key, most significant byte first
+  uint32_t prefix = 0u, pmask = 0u, rank = kp;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int i = lane; i < 256; i += 64) hist[i] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i = lane; i < n; i += 64) {
+      const uint32_t k = key[i];
+      if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // digit d with (count above d) < rank <= (count at or above d)
+    uint32_t acc = 0u;
+    int d = 255;
+    for (; d > 0; --d) {
+      const uint32_t c = hist[d];
+      if (acc + c >= rank) break;
+      acc += c;
+    }
+    rank -= acc;
+    prefix |= (uint32_t)d << shift;
+    pmask |= 255u << shift;
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane == 0) {
+    const float u = 5.9604644775390625e-8f;   // 2^-24
+    const float dd = (float)a.dim;
+    const float gam = dd * u / (1.f - dd * u);
+    const float tol = 2.f * gam * a.qnorm[q] * __uint_as_float(*a.norm_max) * 1.125f + 1e-30f;
+    const float t = key2f(prefix) - tol;
+    atomicMax(a.tau + q, fkey(t));
+  }
+}
+
+#define FR_SEED_CASES(X) \
+  X(kF32, 64) X(kF32, 128) X(kF32, 192) X(kF32, 256) \
+  X(kBF16, 64) X(kBF16, 128) X(kBF16, 192) X(kBF16, 256) \
+  X(kFP8, 64) X(kFP8, 128) X(kFP8, 192) X(kFP8, 256)
+
+hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s) {
+  FR_REQUIRE(a.qlist);
+  FR_REQUIRE(a.n_list);
+  FR_REQUIRE(a.kp);
+  FR_REQUIRE(a.tiles);
+  FR_REQUIRE(a.qtiles);
+  FR_REQUIRE(a.qnorm);
+  FR_REQUIRE(a.norm_max);
+  FR_REQUIRE(a.mw);
+  FR_REQUIRE(a.tau);
+  if (dt == kFP8) {
+    FR_REQUIRE(a.xscale);
+    FR_REQUIRE(a.qscale);
+  }
+  if (a.max_list == 0 || a.n_groups == 0) return hipSuccess;
+#define FR_SEED(D, P)                                                                      \
+  if (dt == D && dpad == P) {                                                              \
+    hipLaunchKernelGGL((k_seed<D, P>), dim3((a.max_list + 3u) / 4u), dim3(256), 0, s, a); \
+    return hipGetLastError();                                                              \
+  }
+  FR_SEED_CASES(FR_SEED)
+#undef FR_SEED
+  return hipErrorInvalidValue;
+}
+
 __global__ void k_zero_work(uint32_t* w) {
   if (threadIdx.x < kXcds) w[threadIdx.x] = 0u;
 }
@@ -478,53 +717,74 @@ hipError_t launch_zero_work(uint32_t* work, hipStream_t s) {
 // Matrix-core products of one tile (A: 32 documents, from the LDS ring)
 // with QB blocks of 32 queries (B, in registers).  The k order inside a
 // 16-byte chunk is the same for both operands, so any fixed pairing of
-// chunks gives the dot products.  A chunks are read from LDS one at a time
-// and used for every query block before the next is read.
+// chunks gives the dot products.  A chunks are read from LDS in groups of G,
+// the next group's reads issued before the current group's matrix
+// instructions (scheduling barriers keep that order), so LDS latency
+// overlaps the matrix work.
 template <int DT, int CH, int QB>
 __device__ __forceinline__ void mma_tile(f32x16 (&acc)[QB], const uint8_t* slot,
                                          const uint4 (&bq)[QB][CH], int lane) {
   const uint4* p = (const uint4*)slot + lane;
-  if constexpr (DT == kF32) {
-    // 32x32x2 FP32: a chunk holds 4 consecutive k values per lane
+  constexpr int G = DT == kF32 ? 2 : (CH % 4 == 0 ? 4 : 2);
+  constexpr int NG = CH / G;
+  static_assert(CH % G == 0 && G % 2 == 0, "chunk groups");
+  uint4 buf[2][G];
+  auto load = [&](int g, uint4 (&d)[G]) {
 #pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const uint4 x = p[j * 64];
+    for (int i = 0; i < G; ++i) d[i] = p[(g * G + i) * 64];
+  };
+  auto work = [&](int g, const uint4 (&x)[G]) {
+    if constexpr (DT == kF32) {
+      // 32x32x2 FP32: a chunk holds 4 consecutive k values per lane
 #pragma unroll
-      for (int b = 0; b < QB; ++b) {
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x.x), __uint_as_float(bq[b][j].x), acc[b], 0, 0, 0);
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x.y), __uint_as_float(bq[b][j].y), acc[b], 0, 0, 0);
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x.z), __uint_as_float(bq[b][j].z), acc[b], 0, 0, 0);
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x.w), __uint_as_float(bq[b][j].w), acc[b], 0, 0, 0);
+      for (int i = 0; i < G; ++i) {
+        const int j = g * G + i;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].x), __uint_as_float(bq[b][j].x), acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].y), __uint_as_float(bq[b][j].y), acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].z), __uint_as_float(bq[b][j].z), acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].w), __uint_as_float(bq[b][j].w), acc[b], 0, 0, 0);
+        }
+      }
+    } else if constexpr (DT == kBF16) {
+      // 32x32x16 BF16: one chunk = the 8 k values of one instruction
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int j = g * G + i;
+#pragma unroll
+        for (int b = 0; b < QB; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x[i]),
+                                                            __builtin_bit_cast(bf16x8, bq[b][j]),
+                                                            acc[b], 0, 0, 0);
+      }
+    } else {
+      // 32x32x64 FP8 (E4M3, format code 0 for both operands, no block
+      // scale): two chunks = the 32 k values of one instruction
+#pragma unroll
+      for (int i = 0; i < G; i += 2) {
+        const int j = g * G + i;
+        const i32x8 av = {(int)x[i].x, (int)x[i].y, (int)x[i].z, (int)x[i].w,
+                          (int)x[i + 1].x, (int)x[i + 1].y, (int)x[i + 1].z, (int)x[i + 1].w};
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+          const i32x8 bv = {(int)bq[b][j].x, (int)bq[b][j].y, (int)bq[b][j].z, (int)bq[b][j].w,
+                            (int)bq[b][j + 1].x, (int)bq[b][j + 1].y, (int)bq[b][j + 1].z,
+                            (int)bq[b][j + 1].w};
+          acc[b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[b], 0, 0, 0, 0, 0, 0);
+        }
       }
     }
-  } else if constexpr (DT == kBF16) {
-    // 32x32x16 BF16: one chunk = the 8 k values of one instruction
+  };
+  load(0, buf[0]);
 #pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const uint4 x = p[j * 64];
-#pragma unroll
-      for (int b = 0; b < QB; ++b)
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x),
-                                                          __builtin_bit_cast(bf16x8, bq[b][j]),
-                                                          acc[b], 0, 0, 0);
-    }
-  } else {
-    // 32x32x64 FP8 (E4M3, format code 0 for both operands, no block scale):
-    // two chunks = the 32 k values of one instruction
-#pragma unroll
-    for (int j = 0; j < CH; j += 2) {
-      const uint4 x0 = p[j * 64], x1 = p[(j + 1) * 64];
-      const i32x8 av = {(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w,
-                        (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
-#pragma unroll
-      for (int b = 0; b < QB; ++b) {
-        const i32x8 bv = {(int)bq[b][j].x, (int)bq[b][j].y, (int)bq[b][j].z, (int)bq[b][j].w,
-                          (int)bq[b][j + 1].x, (int)bq[b][j + 1].y, (int)bq[b][j + 1].z,
-                          (int)bq[b][j + 1].w};
-        acc[b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[b], 0, 0, 0, 0, 0, 0);
-      }
-    }
+  for (int g = 0; g < NG; ++g) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (g + 1 < NG) load(g + 1, buf[(g + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    work(g, buf[g & 1]);
   }
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // Row (within the 32-row tile) of accumulator element v of a lane in half h.
@@ -563,6 +823,21 @@ __device__ __forceinline__ void wg_barrier() {
   __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
   __builtin_amdgcn_s_barrier();
   __asm__ __volatile__("" ::: "memory");
+}
+
+// LDS word access written as inline assembly.  The loader wavefront uses
+// these for its hand-over counters: the compiler cannot tell them apart from
+// the ring its direct-to-LDS loads write, and would otherwise wait for every
+// tile load in flight before each of them.  The load waits for itself only.
+__device__ __forceinline__ uint32_t lds_word_ld(const uint32_t* p) {
+  const uint32_t addr = (uint32_t)(size_t)(const __attribute__((address_space(3))) uint32_t*)p;
+  uint32_t v;
+  __asm__ __volatile__("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(addr) : "memory");
+  return v;
+}
+__device__ __forceinline__ void lds_word_st(uint32_t* p, uint32_t v) {
+  const uint32_t addr = (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t*)p;
+  __asm__ __volatile__("ds_write_b32 %0, %1" : : "v"(addr), "v"(v) : "memory");
 }
 
 // Copy tile `tile` (and its FP8 row scales) into one ring slot.
@@ -650,41 +925,46 @@ __device__ __forceinline__ uint64_t mask_combine(const MaskJob& j, uint32_t info
 // two helpers, and takes work items (a chunk of 1024-document groups x a
 // tile of NW*QB*32 queries) from its XCD's queue:
 //   * the loader wavefront streams every tile of the item's groups into the
-//     LDS ring, a few tiles ahead;
+//     LDS ring, up to PD tiles ahead, and publishes each slot once its
+//     direct-to-LDS loads have landed; with them it copies the predicate
+//     masks of the item's queries (computed beforehand by k_mask_words) for
+//     the next group;
 //   * compute wavefront w owns QB blocks of 32 queries (B operand in
 //     registers).  Per tile it scores the tile on the matrix cores (unless
 //     no query of it matches the tile), drops (doc, query) pairs that fail
-//     the predicate mask or score below the query's threshold, and stages
-//     the rest in LDS.  It also evaluates the next group's predicate masks
-//     for its queries (loads issued a tile ahead);
-//   * the keeper wavefront moves staged candidates to the global per-query
-//     buffers and histograms every F tiles, and raises the thresholds from
-//     the global histograms (a three-stage pipeline, one stage per F tiles,
-//     so its loads have F tiles to arrive).  Compute wavefronts read the
+//     the predicate mask or score below the query's threshold, and appends
+//     the rest to its staging ring in LDS;
+//   * the keeper wavefront, on a fixed clock period, moves staged candidates
+//     to the global per-query buffers and histograms (space reserved in one
+//     period, entries written in the next) and raises the thresholds from
+//     the global histograms (one pipeline stage per period, so every load
+//     it waits for is a period old).  Compute wavefronts read the
 //     thresholds from LDS at every tile.
-// Compute wavefronts thus issue no global atomics and wait on no global
-// loads in the tile loop, except when a staging buffer is full (then they
-// append directly).  One workgroup barrier per tile hands over a ring slot
-// and a staging half; every wavefront executes the same barrier sequence:
-// two per item fetch, one after the item set-up, one per tile, one at the
-// item end.
+// The three kinds of wavefront hand over work through counters in LDS
+// (slot published, tiles done, staging head and tail, item finished), so a
+// slow tile or a long memory round trip in one of them does not stall the
+// others; the ring and the staging rings absorb the difference.  Compute
+// wavefronts issue no global atomics in the tile loop unless their staging
+// ring is full (then they append directly).  All wavefronts meet at
+// workgroup barriers only between items: two per item fetch, one after the
+// item set-up, one at the item end.
 template <int DT, int DPAD, int QB, int NW>
 __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   using R = Ring<DT, DPAD>;
   constexpr int CH = R::CH;                 // 16-byte chunks per lane per tile
   constexpr int QT = NW * QB * 32;          // queries per work item
-  constexpr int MS = kWords + 1;            // padded mask row (bank spread)
-  constexpr int NJ = (QB + 1) / 2;          // mask-job queries per lane
-  constexpr int F = 2;                      // tiles per keeper cycle
-  constexpr int SCH = 256;                  // staged entries per wavefront and half
+  constexpr int LM = QT / 128;              // 1 KB mask loads per word (and per tile)
+  constexpr int LT = R::L + LM;             // loader's loads per tile
+  constexpr int SR = 512;                   // staging ring entries per wavefront
+  constexpr long long kPeriod = 3000;       // keeper period, shader clocks
   constexpr int RJ = QT / 64;               // queries per keeper lane
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   static_assert(QT <= 256, "staged query index is one byte");
-  static_assert((kGroup / kTile) % F == 0, "cycles tile a group");
   __shared__ __attribute__((aligned(16))) uint8_t s_ring[R::NS * R::TB];
   __shared__ __attribute__((aligned(16))) float s_rscale[DT == kFP8 ? R::NS * kTile : 4];
-  __shared__ uint64_t s_mask[QT * MS];
-  __shared__ uint32_t s_lit[QT * kLits];
+  // predicate masks of the current and the next group: [group % 2][word][j]
+  __shared__ __attribute__((aligned(16))) uint64_t s_mask[2][kWords][QT];
+  __shared__ __attribute__((aligned(16))) uint8_t s_msink[LM * 1024];   // target of padding loads
   __shared__ uint32_t s_item;
   // per query of the item, index j = (wave * QB + b) * 32 + col
   __shared__ float s_thr[QT];
@@ -692,12 +972,20 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   __shared__ uint32_t s_qkp[QT];            // selection size
   __shared__ float s_qlo[QT];
   __shared__ float s_qiw[QT];
-  // staging: entries (score key << 32 | slot) and the query's j, by half
-  __shared__ unsigned long long s_sk[2][NW][SCH];
-  __shared__ uint8_t s_sq[2][NW][SCH];
-  __shared__ uint32_t s_sn[2][NW];
+  // ring hand-over: sequence number of the tile in each slot, tiles done
+  // per compute wavefront (sequence numbers run on across items)
+  __shared__ uint32_t s_ready[R::NS];
+  __shared__ uint32_t s_done[NW];
+  __shared__ uint32_t s_fin[NW];            // item number a compute wavefront finished
+  // staging rings: entries (score key << 32 | slot) and the query's j;
+  // head written by the compute wavefront, tail by the keeper
+  __shared__ unsigned long long s_sk[NW][SR];
+  __shared__ uint8_t s_sq[NW][SR];
+  __shared__ uint32_t s_shead[NW];
+  __shared__ uint32_t s_stail[NW];
   // keeper scratch
   __shared__ uint32_t s_hcnt[QT];
+  __shared__ uint32_t s_hcur[QT];
   __shared__ uint32_t s_hbase[QT];
   __shared__ uint32_t s_hmax[QT];
   __shared__ uint32_t s_dirty[QT / 32];
@@ -721,12 +1009,22 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
+  // LDS word written by another wavefront of the workgroup
+  auto lds_get = [](const uint32_t* p) -> uint32_t {
+    return __atomic_load_n(p, __ATOMIC_RELAXED);
+  };
+  auto lds_put = [](uint32_t* p, uint32_t v) {
+    __asm__ __volatile__("" ::: "memory");     // earlier LDS accesses first
+    __atomic_store_n(p, v, __ATOMIC_RELAXED);
+  };
 
   if (wave == NW) {
     // ---------------------------------------------------------- loader
-    // Tile i of an item goes to slot i % NS; it is issued after tile
-    // barrier i - PD, when every compute wavefront is done with the slot's
-    // previous tile (i - NS = i - PD - 1).
+    // Tile seq goes to slot seq % NS.  It is issued once every compute
+    // wavefront is done with the slot's previous tile (seq - NS) and fewer
+    // than PD tiles are in flight; the oldest tile in flight is published
+    // (its slot's sequence number set) once its loads have landed.
+    uint32_t seq0 = 0;                                // first tile of the item
     for (;;) {
       wg_barrier();
       const uint32_t item = s_item;
@@ -736,19 +1034,67 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       item_range(item, g0, g1);
       const uint32_t n_t = (uint32_t)(g1 - g0) * (kGroup / kTile);
       const uint64_t tile0 = g0 * (uint64_t)(kGroup / kTile);
-      for (uint32_t i = 0; i < (uint32_t)R::PD && i < n_t; ++i)
-        dma_tile<DT, CH>(a.tiles, a.xscale, tile0 + i, s_ring + (i % R::NS) * R::TB,
-                         s_rscale + (i % R::NS) * kTile, lane);
+      const uint32_t qt = item % n_qtiles;
+      // mask words of group g (item-relative gi) into buffer (seq of its
+      // first tile / 32) % 2: the first group's before its first tile, the
+      // others word by word with the second half of the previous group's
+      // tiles (by then every compute wavefront has left the group that used
+      // the buffer before); other tiles carry padding loads, so that every
+      // tile is LT loads
+      auto dma_mask = [&](uint32_t gi, int w) {
+        const uint32_t buf = ((seq0 >> 5) + gi) & 1u;
+        const uint64_t* src = a.mw + ((g0 + gi) * kWords + (uint64_t)w) * a.ppad +
+                              (uint64_t)qt * QT + 2u * lane;
+#pragma unroll
+        for (int k = 0; k < LM; ++k)
+          __builtin_amdgcn_global_load_lds((const void*)(src + 128 * k),
+                                           (__attribute__((address_space(3))) void*)
+                                               ((uint8_t*)&s_mask[buf][w][0] + 1024 * k),
+                                           16, 0, 0);
+      };
+      auto dma_pad = [&]() {
+#pragma unroll
+        for (int k = 0; k < LM; ++k)
+          __builtin_amdgcn_global_load_lds((const void*)(a.mw + 2u * lane),
+                                           (__attribute__((address_space(3))) void*)
+                                               (s_msink + 1024 * k),
+                                           16, 0, 0);
+      };
+      for (int w = 0; w < kWords; ++w) dma_mask(0u, w);
       wg_barrier();                                   // set-up
-      for (uint32_t i = 0; i < n_t; ++i) {
-        const uint32_t left = n_t - 1 - i;
-        wait_tiles<R::L, R::PD>(left < (uint32_t)(R::PD - 1) ? left : (uint32_t)(R::PD - 1));
-        wg_barrier();                                 // tile i
-        const uint32_t nx = i + R::PD;
-        if (nx < n_t)
-          dma_tile<DT, CH>(a.tiles, a.xscale, tile0 + nx, s_ring + (nx % R::NS) * R::TB,
-                           s_rscale + (nx % R::NS) * kTile, lane);
+      uint32_t issued = 0, published = 0;
+      while (published < n_t) {
+        bool moved = false;
+        while (issued < n_t && issued - published < (uint32_t)R::PD) {
+          const uint32_t sq = seq0 + issued;
+          if (sq >= (uint32_t)R::NS) {
+            uint32_t mind = 0xFFFFFFFFu;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+              const uint32_t d = lds_word_ld(&s_done[w]);
+              mind = d < mind ? d : mind;
+            }
+            if (mind < sq - (uint32_t)R::NS + 1u) break;   // slot still in use
+          }
+          const uint32_t slot = sq % (uint32_t)R::NS;
+          const uint32_t gi = issued >> 5, t = issued & 31u;
+          if (t >= 16u && gi + 1u < n_t / 32u) dma_mask(gi + 1u, (int)(t - 16u));
+          else dma_pad();
+          dma_tile<DT, CH>(a.tiles, a.xscale, tile0 + issued, s_ring + slot * R::TB,
+                           s_rscale + slot * kTile, lane);
+          ++issued;
+          moved = true;
+        }
+        if (published < issued) {
+          wait_tiles<LT, R::PD>(issued - published - 1u);
+          const uint32_t sq = seq0 + published;
+          if (lane == 0) lds_word_st(&s_ready[sq % (uint32_t)R::NS], sq);
+          ++published;
+          moved = true;
+        }
+        if (!moved) __builtin_amdgcn_s_sleep(1);
       }
+      seq0 += n_t;
       wg_barrier();                                   // item end
     }
     return;
@@ -756,35 +1102,49 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
 
   if (wave == NW + 1) {
     // ---------------------------------------------------------- keeper
-    // Move the staged entries of one half to the global buffers: count per
-    // query, reserve space with one atomic per query, scatter, add the
-    // histogram buckets, raise the running maximum.
-    auto flush_half = [&](int h) {
-      uint32_t n[NW];
+    // Moving staged entries to the global buffers takes two periods: count
+    // the new entries per query and reserve global space (one atomic per
+    // query, whose result is used a period later), then scatter them, add
+    // their histogram buckets and raise the running maximum.
+    uint32_t rbase[RJ];           // reserved global position, per query of the lane
+    uint32_t rres = 0;            // bit r: rbase[r] is pending
+    bool pend = false;            // entries [p0, p1) of every ring are reserved
+    uint32_t p0[NW], p1[NW];
+    auto count_reserve = [&]() {
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
-        const uint32_t c = s_sn[h][w];
-        n[w] = c < (uint32_t)SCH ? c : (uint32_t)SCH;
+        p0[w] = lds_get(&s_stail[w]);
+        p1[w] = lds_get(&s_shead[w]);
+        for (uint32_t i = p0[w] + lane; i < p1[w]; i += 64)
+          atomicAdd(&s_hcnt[s_sq[w][i % SR]], 1u);
       }
-#pragma unroll
-      for (int w = 0; w < NW; ++w)
-        for (uint32_t i = lane; i < n[w]; i += 64) atomicAdd(&s_hcnt[s_sq[h][w][i]], 1u);
       wave_sync();
-      for (int j = lane; j < QT; j += 64) {
+      rres = 0;
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) {
+        const int j = lane + 64 * r;
         const uint32_t c = s_hcnt[j];
         if (c) {
-          s_hbase[j] = atomicAdd(a.cnt + s_qg[j], c);
+          rbase[r] = atomicAdd(a.cnt + s_qg[j], c);
+          rres |= 1u << r;
           atomicOr(&s_dirty[j >> 5], 1u << (j & 31));
         }
         s_hcnt[j] = 0u;
       }
+      pend = true;
+      wave_sync();
+    };
+    auto scatter = [&]() {
+#pragma unroll
+      for (int r = 0; r < RJ; ++r)
+        if ((rres >> r) & 1u) s_hbase[lane + 64 * r] = rbase[r];
       wave_sync();
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
-        for (uint32_t i = lane; i < n[w]; i += 64) {
-          const uint32_t j = s_sq[h][w][i];
-          const unsigned long long key = s_sk[h][w][i];
-          const uint32_t r = atomicAdd(&s_hcnt[j], 1u);
+        for (uint32_t i = p0[w] + lane; i < p1[w]; i += 64) {
+          const uint32_t j = s_sq[w][i % SR];
+          const unsigned long long key = s_sk[w][i % SR];
+          const uint32_t r = atomicAdd(&s_hcur[j], 1u);
           const uint32_t pos = s_hbase[j] + r;
           const uint32_t qg = s_qg[j];
           if (pos < a.cap) a.cand_key[(uint64_t)qg * a.cap + pos] = key;
@@ -802,9 +1162,16 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
         const uint32_t m = s_hmax[j];
         if (m) atomicMax(a.smax + s_qg[j], m);
         s_hmax[j] = 0u;
-        s_hcnt[j] = 0u;
+        s_hcur[j] = 0u;
       }
-      if (lane < NW) s_sn[h][lane] = 0u;
+      // the entries are consumed: hand their ring space back
+      if (lane < NW) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+          if (w == lane) lds_put(&s_stail[w], p1[w]);
+      }
+      rres = 0;
+      pend = false;
       wave_sync();
     };
 
@@ -910,52 +1277,49 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       }
     };
 
+    uint32_t item_no = 0;
     for (;;) {
       wg_barrier();
       const uint32_t item = s_item;
       wg_barrier();
       if (item >= my_items) break;
-      uint64_t g0, g1;
-      item_range(item, g0, g1);
-      const uint32_t n_t = (uint32_t)(g1 - g0) * (kGroup / kTile);
       wg_barrier();                                   // set-up: s_qg, s_thr valid
       for (int i = lane; i < QT / 32; i += 64) s_dirty[i] = 0u;
       for (int j = lane; j < QT; j += 64) {
         s_hcnt[j] = 0u;
+        s_hcur[j] = 0u;
         s_hmax[j] = 0u;
       }
       rstage = 0;
+      pend = false;
+      rres = 0;
       wave_sync();
-      for (uint32_t i = 0; i < n_t; ++i) {
-        wg_barrier();                                 // tile i
-        if (i % F == 0 && i > 0) {
-          // the previous cycle's half is complete.  While some query has no
-          // threshold yet (the first cycles of an item), run a whole
-          // refresh round at once: until then every match is a candidate.
-          refresh_consume();
-          flush_half((int)((i / F - 1) & 1u));
-          bool cold = false;
-          if (i <= 4 * F) {
+      long long last = (long long)__builtin_readcyclecounter();
+      for (uint32_t period = 1;; ++period) {
+        // wait for the next period (or the end of the item's tiles)
+        bool fin;
+        for (;;) {
+          fin = true;
 #pragma unroll
-            for (int r = 0; r < RJ; ++r) {
-              const int j = lane + 64 * r;
-              cold = cold || (s_qg[j] != kNone && s_thr[j] == -INFINITY);
-            }
-          }
-          if (__ballot(cold)) {
-            refresh_drain();
-            refresh_issue();
-            refresh_drain();
-          } else {
-            refresh_issue();
-          }
+          for (int w = 0; w < NW; ++w) fin = fin && lds_get(&s_fin[w]) == item_no;
+          if (fin || (long long)__builtin_readcyclecounter() - last >= kPeriod) break;
+          __builtin_amdgcn_s_sleep(2);
         }
+        last = (long long)__builtin_readcyclecounter();
+        refresh_consume();
+        if (pend) scatter();
+        count_reserve();
+        if (fin) {
+          // every compute wavefront is done with the item: move the rest
+          scatter();
+          if (rstage == 2) refresh_issue();
+          refresh_drain();
+          break;
+        }
+        refresh_issue();
       }
+      ++item_no;
       wg_barrier();                                   // item end
-      refresh_consume();
-      flush_half((int)((n_t / F - 1) & 1u));
-      if (rstage == 2) refresh_issue();
-      refresh_drain();
     }
     return;
   }
@@ -967,75 +1331,26 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   uint32_t qi[QB], kp[QB];
   float thr[QB], hlo[QB], hinv[QB], qs[QB];
   bool qv[QB];
-  // mask jobs: this lane evaluates blocks b = half + 2j (j < NJ), column col;
-  // their literal terms live in s_lit
-  uint32_t jinfo[NJ], jq[NJ], jcnt[NJ];
-  bool jv[NJ];
-  if (wave == 0)
-    for (int i = lane; i < 2 * NW; i += 64) s_sn[i / NW][i % NW] = 0u;
+  if (wave == 0) {
+    for (int i = lane; i < R::NS; i += 64) s_ready[i] = 0xFFFFFFFFu;
+    for (int i = lane; i < NW; i += 64) {
+      s_done[i] = 0u;
+      s_fin[i] = 0xFFFFFFFFu;
+      s_shead[i] = 0u;
+      s_stail[i] = 0u;
+    }
+  }
+  uint32_t seq0 = 0;            // sequence number of the item's first tile
+  uint32_t item_no = 0;
+  uint32_t shead = 0;           // this wavefront's staging head (it is the only writer)
 
   auto my_pos = [&](uint32_t qt, int b) -> uint32_t {
     return qt * QT + (uint32_t)((wave * QB + b) * 32 + col);
   };
   auto my_j = [&](int b) -> int { return (wave * QB + b) * 32 + col; };
-  auto smask = [&](int b, int c, int w) -> uint64_t& {
-    return s_mask[((wave * QB + b) * 32 + c) * MS + w];
-  };
-  auto jterms = [&](int j) -> const uint32_t* {
-    return s_lit + ((wave * QB + half + 2 * j) * 32 + col) * kLits;
-  };
-
-  // load the literal tables of this lane's mask-job queries for tile qt
-  auto load_jobs = [&](uint32_t qt) {
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int b = half + 2 * j;
-      const uint32_t pos = my_pos(qt, b);
-      jv[j] = b < QB && pos < n_list;
-      const uint32_t q = jv[j] ? a.qlist[pos] : 0u;
-      jq[j] = q;
-      jinfo[j] = jv[j] ? a.linfo[q] : 0u;
-      jcnt[j] = 0u;
-      if (b < QB) {
-        const uint4* t = (const uint4*)(a.lit + (uint64_t)q * kLits);
-        uint4* d = (uint4*)(s_lit + ((wave * QB + b) * 32 + col) * kLits);
-#pragma unroll
-        for (int i = 0; i < kLits / 4; ++i) d[i] = jv[j] ? t[i] : make_uint4(0, 0, 0, 0);
-      }
-    }
-  };
-  auto flush_counts = [&]() {
-    if (!a.count_matches) return;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      if (jv[j] && jcnt[j]) atomicAdd(a.nmatch + jq[j], (unsigned long long)jcnt[j]);
-  };
-  // evaluate words w and w+1 of group g for the lane's jobs (loads of both
-  // words in flight together)
-  auto masks_words_sync = [&](uint64_t g, int w) {
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int b = half + 2 * j;
-      if (b < QB) {
-        uint64_t m0 = 0ull, m1 = 0ull;
-        if (jv[j]) {
-          if (lit_slow(jinfo[j])) {
-            m0 = cnf_word(a.live, a.bits, a.vocab, g, w, jq[j], a.clause_off, a.literal_off, a.terms);
-            m1 = cnf_word(a.live, a.bits, a.vocab, g, w + 1, jq[j], a.clause_off, a.literal_off,
-                          a.terms);
-          } else {
-            MaskJob x0, x1;
-            mask_issue(x0, a.bits, a.live, a.vocab, g, w, jinfo[j], jterms(j));
-            mask_issue(x1, a.bits, a.live, a.vocab, g, w + 1, jinfo[j], jterms(j));
-            m0 = mask_combine(x0, jinfo[j]);
-            m1 = mask_combine(x1, jinfo[j]);
-          }
-        }
-        jcnt[j] += (uint32_t)(__popcll(m0) + __popcll(m1));
-        smask(b, col, w) = m0;
-        smask(b, col, w + 1) = m1;
-      }
-    }
+  // mask word w of this lane's query in block b, group buffer mb
+  auto smask = [&](int mb, int b, int w) -> uint64_t {
+    return s_mask[mb][w][(wave * QB + b) * 32 + col];
   };
   auto load_queries = [&](uint32_t qt) {
 #pragma unroll
@@ -1066,7 +1381,6 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
 
   // ------------------------------------------------------------ items
   uint32_t cur_qt = 0xFFFFFFFFu;
-  uint64_t pending_g = ~0ull;   // group whose masks are already in LDS
   for (;;) {
     if (tid == 0) s_item = atomicAdd(a.work + xcd, 1u);
     wg_barrier();
@@ -1078,20 +1392,17 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     item_range(item, g0, g1);
 
     if (qt != cur_qt) {
-      if (cur_qt != 0xFFFFFFFFu) flush_counts();
       cur_qt = qt;
       load_queries(qt);
-      load_jobs(qt);
-      pending_g = ~0ull;
-    }
-    if (pending_g != g0) {
-#pragma unroll 1
-      for (int w = 0; w < kWords; w += 2) masks_words_sync(g0, w);
     }
     wg_barrier();                                     // set-up
 
     for (uint64_t g = g0; g < g1; ++g) {
-      const bool has_next = g + 1 < g1;
+      const uint32_t ti0 = (uint32_t)(g - g0) * (kGroup / kTile);   // item-relative tile
+      // the group's masks have landed once its first tile is published
+      const uint32_t sq0 = seq0 + ti0;
+      while (lds_get(&s_ready[sq0 % (uint32_t)R::NS]) != sq0) __builtin_amdgcn_s_sleep(1);
+      const int mb = (int)((sq0 >> 5) & 1u);
       // tiles of this group that some query of this wavefront matches
       uint32_t act = 0;
 #pragma unroll 1
@@ -1099,53 +1410,23 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
         uint64_t o = 0;
 #pragma unroll
         for (int b = 0; b < QB; ++b)
-          if (kp[b]) o |= smask(b, col, w);
+          if (kp[b]) o |= smask(mb, b, w);
         if (__ballot((uint32_t)o != 0u)) act |= 1u << (2 * w);
         if (__ballot((uint32_t)(o >> 32) != 0u)) act |= 2u << (2 * w);
       }
 
       const uint64_t tile0 = g * (uint64_t)(kGroup / kTile);
-      // next-group mask pipeline: word `mw_fly` has loads in flight
-      int mw_next = has_next ? 0 : kWords;   // next word to issue
-      int mw_fly = -1;                        // word in flight
-      MaskJob mj[NJ];
-      auto mask_issue_word = [&](int w) {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          if (jv[j] && !lit_slow(jinfo[j]))
-            mask_issue(mj[j], a.bits, a.live, a.vocab, g + 1, w, jinfo[j], jterms(j));
-        mw_fly = w;
-      };
-      auto mask_finish_word = [&]() {
-        const int w = mw_fly;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int b = half + 2 * j;
-          if (b < QB) {
-            uint64_t m = 0ull;
-            if (jv[j])
-              m = lit_slow(jinfo[j]) ? cnf_word(a.live, a.bits, a.vocab, g + 1, w, jq[j],
-                                                a.clause_off, a.literal_off, a.terms)
-                                     : mask_combine(mj[j], jinfo[j]);
-            jcnt[j] += (uint32_t)__popcll(m);
-            smask(b, col, w) = m;
-          }
-        }
-        mw_fly = -1;
-      };
-
       // one step per tile of the group: wait for the tile's ring slot, then
       // (if a query of this wavefront matches the tile) score it
-      const uint32_t ti0 = (uint32_t)(g - g0) * (kGroup / kTile);   // item-relative tile
       auto body = [&](int t) {
-        const uint32_t ti = ti0 + (uint32_t)t;
-        const uint32_t rs = ti % (uint32_t)R::NS;
-        const int h = (int)((ti / F) & 1u);
-        wg_barrier();
-        // words whose current-group tiles are all behind us can be replaced
-        if (mw_fly >= 0 && 2 * mw_fly + 1 < t) mask_finish_word();
-        if (mw_fly < 0 && mw_next < kWords && mw_next <= (t >> 1) + 1) mask_issue_word(mw_next++);
-        if (!((act >> t) & 1u)) return;
+        const uint32_t sq = seq0 + ti0 + (uint32_t)t;
+        const uint32_t rs = sq % (uint32_t)R::NS;
+        // wait until the loader has published the tile
+        while (lds_get(&s_ready[rs]) != sq) __builtin_amdgcn_s_sleep(1);
+        if (!((act >> t) & 1u)) {
+          lds_put(&s_done[wave], sq + 1u);
+          return;
+        }
 #pragma unroll
         for (int b = 0; b < QB; ++b) thr[b] = s_thr[my_j(b)];
         f32x16 accs[QB];
@@ -1159,7 +1440,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
           f32x16& acc = accs[b];
-          const uint32_t m32 = (uint32_t)(smask(b, col, t >> 1) >> ((t & 1) * 32));
+          const uint32_t m32 = (uint32_t)(smask(mb, b, t >> 1) >> ((t & 1) * 32));
           if constexpr (DT == kFP8) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
@@ -1180,23 +1461,32 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
               for (int v = 0; v < 16; ++v)
                 if (((m32 >> acc_row(v, half)) & 1u) && s[v] >= thr[b]) pm |= 1u << v;
             }
-            if (pm) {
-              const uint32_t p0 = atomicAdd(&s_sn[h][wave], (uint32_t)__popc(pm));
+            {
+              // wave-wide compaction: the v-th survivors of all lanes take
+              // consecutive staging slots (this wavefront is the only writer
+              // of its buffer, so the count needs no atomic)
               const uint32_t q = qi[b];
               const int jj = my_j(b);
-              uint32_t r = 0;
+              const uint32_t room = (uint32_t)SR - (shead - lds_get(&s_stail[wave]));
+              uint32_t base = 0;
 #pragma unroll
               for (int v = 0; v < 16; ++v) {
-                if ((pm >> v) & 1u) {
+                const bool on = (pm >> v) & 1u;
+                const uint64_t bal = __ballot(on);
+                if (bal == 0ull) continue;
+                const uint32_t idx = base + __builtin_amdgcn_mbcnt_hi(
+                                                (uint32_t)(bal >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                base += (uint32_t)__popcll(bal);
+                if (on) {
                   const uint64_t slot = (tile0 + t) * kTile + acc_row(v, half);
                   const uint32_t k32 = fkey(s[v]);
                   // the id (for the tie order) is looked up by the selection
                   const unsigned long long key =
                       ((unsigned long long)k32 << 32) | (unsigned long long)slot;
-                  const uint32_t idx = p0 + r++;
-                  if (idx < (uint32_t)SCH) {
-                    s_sk[h][wave][idx] = key;
-                    s_sq[h][wave][idx] = (uint8_t)jj;
+                  if (idx < room) {
+                    s_sk[wave][(shead + idx) % SR] = key;
+                    s_sq[wave][(shead + idx) % SR] = (uint8_t)jj;
                   } else {
                     // staging full: append directly
                     const uint32_t pos = atomicAdd(a.cnt + q, 1u);
@@ -1211,24 +1501,24 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
                   }
                 }
               }
+              shead += base < room ? base : room;
             }
           }
+        }
+        if (lane == 0) {
+          lds_put(&s_shead[wave], shead);
+          lds_put(&s_done[wave], sq + 1u);
         }
       };
 
 #pragma unroll 1
       for (int t = 0; t < kGroup / kTile; ++t) body(t);
-      // finish the next group's masks
-      if (mw_fly >= 0) mask_finish_word();
-      while (mw_next < kWords) {
-        mask_issue_word(mw_next++);
-        mask_finish_word();
-      }
-      pending_g = has_next ? g + 1 : ~0ull;
     }
+    seq0 += (uint32_t)(g1 - g0) * (kGroup / kTile);
+    if (lane == 0) lds_put(&s_fin[wave], item_no);
+    ++item_no;
     wg_barrier();                                     // item end
   }
-  if (cur_qt != 0xFFFFFFFFu) flush_counts();
 }
 
 // (dtype, padded dim, query blocks per wavefront, wavefronts per workgroup)
@@ -1262,13 +1552,8 @@ hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int 
   FR_REQUIRE(a.hlo);
   FR_REQUIRE(a.hinvw);
   FR_REQUIRE(a.cand_key);
-  FR_REQUIRE(a.nmatch);
   FR_REQUIRE(a.work);
-  FR_REQUIRE(a.clause_off);
-  FR_REQUIRE(a.literal_off);
-  FR_REQUIRE(a.terms);
-  FR_REQUIRE(a.lit);
-  FR_REQUIRE(a.linfo);
+  FR_REQUIRE(a.mw);
   if (dt == kFP8) {
     FR_REQUIRE(a.xscale);
     FR_REQUIRE(a.qscale);

@@ -92,6 +92,7 @@ struct Workspace {
   float* hinvw = nullptr;
   unsigned long long* nmatch = nullptr;
   unsigned long long* cand_key = nullptr;
+  uint64_t* mw = nullptr;    // predicate masks of the current pass
   unsigned long long* sel_key = nullptr;
   uint32_t* sel_slot = nullptr;
   uint32_t* out_ids = nullptr;
@@ -172,6 +173,9 @@ struct fr_index {
   std::vector<std::pair<uint32_t, uint32_t>> history;  // (workspace, ring slot) per call
   std::mutex mu;
 };
+
+// row stride (positions) of a workspace's predicate-mask buffer
+static uint32_t mask_ppad(const fr_index* ix) { return round_up(ix->qmax, 256); }
 
 namespace {
 
@@ -364,6 +368,44 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   pa.linfo = w.linfo;
   FR_HIP(launch_prep(pa, s));
 
+  MaskWordArgs ma{};
+  ma.qlist = w.qlist;
+  ma.n_list = w.desc + 1;
+  ma.max_list = ix->qmax;
+  ma.ppad = mask_ppad(ix);
+  ma.n_groups = n_groups;
+  ma.gpt = std::max<uint32_t>(1, std::min<uint32_t>(16, (uint32_t)(((uint64_t)n_groups * ix->qmax) >> 18)));
+  ma.live = ix->live;
+  ma.bits = ix->bits;
+  ma.vocab = ix->cfg.vocab;
+  ma.lit = w.lit;
+  ma.linfo = w.linfo;
+  ma.clause_off = w.clause_off;
+  ma.literal_off = w.literal_off;
+  ma.terms = w.terms;
+  ma.mw = w.mw;
+  ma.nmatch = w.nmatch;
+  ma.count_matches = 1;
+  FR_HIP(launch_mask_words(ma, s));
+
+  SeedArgs sd{};
+  sd.qlist = w.qlist;
+  sd.n_list = w.desc + 1;
+  sd.max_list = ix->qmax;
+  sd.kp = w.kp;
+  sd.tiles = ix->tiles;
+  sd.xscale = ix->xscale;
+  sd.qtiles = w.qtiles;
+  sd.qscale = w.qscale;
+  sd.qnorm = w.qnorm;
+  sd.norm_max = ix->norm_max;
+  sd.mw = w.mw;
+  sd.ppad = ma.ppad;
+  sd.n_groups = n_groups;
+  sd.dim = ix->dim;
+  sd.tau = w.tau;
+  FR_HIP(launch_seed(sd, ix->dt, ix->dpad, s));
+
   ScanArgs sa{};
   sa.tiles = ix->tiles;
   sa.xscale = ix->xscale;
@@ -384,15 +426,10 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sa.hinvw = w.hinvw;
   sa.cand_key = w.cand_key;
   sa.cap = ix->cand_cap;
-  sa.nmatch = w.nmatch;
   sa.work = w.work;
   sa.gpi = (uint32_t)gpi;
-  sa.count_matches = 1;
-  sa.clause_off = w.clause_off;
-  sa.literal_off = w.literal_off;
-  sa.terms = w.terms;
-  sa.lit = w.lit;
-  sa.linfo = w.linfo;
+  sa.mw = w.mw;
+  sa.ppad = ma.ppad;
   if (timing) FR_HIP(hipEventRecord(w.e_scan0, s));
   FR_HIP(launch_scan(sa, ix->dt, ix->dpad, qb, nw, ix->n_wg, s));
   if (timing) FR_HIP(hipEventRecord(w.e_scan1, s));
@@ -439,10 +476,14 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   ra.hinvw = w.hinvw;
   ra.work = w.work;
   FR_HIP(launch_rerun(ra, s));
+  MaskWordArgs mb = ma;
+  mb.qlist = w.qlist2;
+  mb.n_list = w.desc + 2;
+  mb.count_matches = 0;
+  FR_HIP(launch_mask_words(mb, s));
   ScanArgs sb = sa;
   sb.qlist = w.qlist2;
   sb.n_list = w.desc + 2;
-  sb.count_matches = 0;
   FR_HIP(launch_scan(sb, ix->dt, ix->dpad, qb, nw, ix->n_wg, s));
   SelectArgs sf = se;
   sf.qlist = w.qlist2;
@@ -674,6 +715,7 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(dalloc(&w.hinvw, qm, D));
     FR_ALLOC(dalloc(&w.nmatch, qm, D));
     FR_ALLOC(dalloc(&w.cand_key, (size_t)qm * ix->cand_cap, D));
+    FR_ALLOC(dalloc(&w.mw, (size_t)(ix->cap / kGroup) * kWords * mask_ppad(ix), D));
     FR_ALLOC(dalloc(&w.sel_key, (size_t)qm * ix->rmax, D));
     FR_ALLOC(dalloc(&w.sel_slot, (size_t)qm * ix->rmax, D));
     FR_ALLOC(dalloc(&w.out_ids, (size_t)qm * cfg->k_max, D));

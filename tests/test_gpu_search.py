@@ -304,19 +304,35 @@ def test_update_errors_leave_index_unchanged(tiny):
 def test_candidate_overflow_second_pass_and_tie_limit():
     from paper_2402_13435_amd import FrError, Index
     from paper_2402_13435_amd.binding import FR_EUNSUPPORTED
-    # One predicate group (1,000 docs, every doc matches): the first 32-doc
-    # tile appends 32 candidates per query before any threshold exists, and
-    # later tiles add more, so a 32-entry buffer overflows on the first pass;
-    # the second pass starts from the first pass's threshold and fits.
-    cfg = datagen.scaled(datagen.CONFIGS["tiny"], 1000, 16)
-    c = datagen.corpus(cfg)
-    qb = datagen.queries(cfg)
+    # Six predicate groups, every document matches; the query is e_0 and a
+    # document's score is its first coordinate: ~0 in the first four groups
+    # (the sample the starting threshold comes from), spread over 0.5..0.99
+    # in the last two.  The starting threshold is therefore low, the last
+    # groups append far more than the 64-entry buffer holds, and the second
+    # pass (from the first pass's histogram) fits.
+    cfg = datagen.scaled(datagen.CONFIGS["tiny"], 6144, 4)
+    rng = np.random.default_rng(7)
+    n, d = 6144, cfg.dim
+    emb = rng.standard_normal((n, d)).astype(np.float32)
+    emb[:, 0] = 0.0
+    emb /= np.linalg.norm(emb, axis=1, keepdims=True)
+    hi = np.linspace(0.5, 0.99, 2048, dtype=np.float64)
+    rng.shuffle(hi)
+    emb[4096:] *= np.sqrt(1.0 - hi ** 2)[:, None].astype(np.float32)
+    emb[4096:, 0] = hi.astype(np.float32)
+    ids = np.arange(n, dtype=np.uint32) * 3 + 1
+    term_off = np.arange(n + 1, dtype=np.int64)
+    terms = np.zeros(n, np.uint32)
+    from types import SimpleNamespace
+    c = SimpleNamespace(emb=emb, ids=ids, term_off=term_off, terms=terms, n=n, cfg=cfg)
     o = oracle_for(c)
-    ix = gpu_index(c, k_max=16, cand_cap=32)
-    empty = datagen.from_cnf_lists(qb.emb, [[]] * qb.n, [16] * qb.n)
-    res = ix.search(qb.emb, empty, 16)
+    ix = gpu_index(c, k_max=16, cand_cap=64)
+    qe = np.zeros((4, d), np.float32)
+    qe[:, 0] = 1.0
+    empty = datagen.from_cnf_lists(qe, [[]] * 4, [16] * 4)
+    res = ix.search(qe, empty, 16)
     assert ix.stats().n_passes == 2
-    for q in range(qb.n):
+    for q in range(4):
         check_query(o, empty, q, res, 16)
     # 200 identical rows tie above any threshold: more than the buffer holds
     emb = np.repeat(c.emb[:1], 200, axis=0)
