@@ -80,8 +80,10 @@ def cpu_baseline(c, qb, k: int, budget_s: float):
 
 def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None):
     from paper_2402_13435_amd import Index, SearchResult
+    # two workspaces: the host prepares the next search while the device runs
+    # the current one
     ix = Index(c.n, c.cfg.dim, c.cfg.vocab, k, dtype=dtype, rescore_r=rescore_r,
-               max_batch=qb.n)
+               max_batch=qb.n, n_workspaces=2)
     ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
     if tiling:
         ix.set_tiling(*tiling)
@@ -94,7 +96,7 @@ def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None):
                        torch.empty((n_q, k), dtype=torch.float32, device=dev),
                        torch.empty(n_q, dtype=torch.int32, device=dev),
                        torch.empty(n_q, dtype=torch.int64, device=dev))
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()   # searches are asynchronous on their own stream
     for _ in range(warmup):
         ix.search(q, qb, k, out=out, stream=stream)
     torch.cuda.synchronize()
@@ -161,7 +163,7 @@ def timed_search(torch, ix, qb, k, steps, warmup, graph=False):
                        torch.empty((n_q, ix.k_max), dtype=torch.float32, device=dev),
                        torch.empty(n_q, dtype=torch.int32, device=dev),
                        torch.empty(n_q, dtype=torch.int64, device=dev))
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()   # searches are asynchronous on their own stream
     for _ in range(warmup):
         ix.search(q, qb, k, out=out, stream=stream, graph=graph)
     torch.cuda.synchronize()
@@ -197,7 +199,8 @@ def bench_precision(args, torch):
     forms = {}
     for dt, r in (("f32", 0), ("bf16", 4096), ("fp8", 4096)):
         log(f"{dt} index")
-        ix = Index(c.n, cfg.dim, cfg.vocab, k, dtype=dt, rescore_r=r, max_batch=qb.n)
+        ix = Index(c.n, cfg.dim, cfg.vocab, k, dtype=dt, rescore_r=r, max_batch=qb.n,
+                   n_workspaces=2)
         ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
         til = ix.autotune(qb.emb, qb, k)
         t = timed_search(torch, ix, qb, k, args.steps, args.warmup)
@@ -239,7 +242,7 @@ def bench_batching(args, torch):
     log(f"oracle on {len(sample)} stratified queries")
     o, res, cpu_s = oracle_sample(c, qb, sample, lambda q: qb.k[q])
     ix = Index(c.n, cfg.dim, cfg.vocab, 1000, dtype="bf16", rescore_r=4096, rescore_min=1024,
-               max_batch=qb.n)
+               max_batch=qb.n, n_workspaces=2)
     ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
     til = ix.autotune(qb.emb, qb, qb.k)
     t = timed_search(torch, ix, qb, qb.k, args.steps, args.warmup, graph=True)

@@ -63,6 +63,8 @@ typedef enum {
                               device sequence (captured on first use and again whenever
                               the tiling, corpus extent or output pointers change); the
                               call's fr_timings entry then has scan_ms == total_ms */
+#define FR_ASYNC       8u  /* fr_search: enqueue on `stream` and return even when `stream`
+                              is NULL (then the null stream); needs FR_DEVICE_PTRS */
 
 typedef struct {
   uint64_t capacity;       /* maximum live documents (slots); rounded up to 1024 */
@@ -161,10 +163,11 @@ fr_status fr_update_docs(fr_index* ix, uint64_t n_del, const uint32_t* del_ids,
  *            the FP32 rescored value), then -INFINITY.
  * out_count: n_q entries, min(k[q], n_match[q]).
  * out_nmatch:n_q entries, live documents satisfying the predicate.
- * stream:    NULL -> synchronous on the index's stream.  Otherwise a
- *            hipStream_t; the call is enqueued and returns, and requires
+ * stream:    NULL without FR_ASYNC -> synchronous on the index's stream.
+ *            Otherwise a hipStream_t (NULL with FR_ASYNC: the null
+ *            stream); the call is enqueued and returns, and requires
  *            FR_DEVICE_PTRS (inputs and outputs stay valid until the
- *            stream passes the call).
+ *            stream passes the call).  FR_GRAPH needs a non-null stream.
  * For BF16/FP8 indexes the approximate scores select the best min(R_q,
  * n_match) candidates by (approximate score desc, id asc), which are
  * rescored in FP32 and ordered by (FP32 score desc, id asc).

@@ -22,7 +22,7 @@ FR_ENOTFOUND, FR_EUNSUPPORTED, FR_EDEVICE, FR_EBUSY = -5, -6, -7, -8
 STATUS_NAMES = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_ECAPACITY",
                 -4: "FR_EDUPID", -5: "FR_ENOTFOUND", -6: "FR_EUNSUPPORTED",
                 -7: "FR_EDEVICE", -8: "FR_EBUSY"}
-FR_DEVICE_PTRS, FR_NOWAIT, FR_GRAPH = 1, 2, 4
+FR_DEVICE_PTRS, FR_NOWAIT, FR_GRAPH, FR_ASYNC = 1, 2, 4, 8
 DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -250,7 +250,7 @@ class Index:
         k = _host(np.broadcast_to(np.asarray(k, dtype=np.uint32), (n_q,)), np.uint32)
         dev = _is_dev(queries)
         flags = ((FR_DEVICE_PTRS if dev else 0) | (FR_NOWAIT if nowait else 0) |
-                 (FR_GRAPH if graph else 0))
+                 (FR_GRAPH if graph else 0) | (FR_ASYNC if dev and stream is not None else 0))
         if dev:
             if out is None:
                 import torch

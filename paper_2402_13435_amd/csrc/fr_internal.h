@@ -16,6 +16,8 @@ constexpr int kHist = kNBC + kNBF;   // u32 counters per query histogram
 constexpr int kXcds = 8;             // work queues (one per XCD)
 constexpr int kSelCap = 8192;        // candidates sorted in LDS by the select kernel
 constexpr int kMaxR = 4096;          // largest K / R handled by select and rescore
+constexpr int kSeedGroups = 4;     // corpus groups sampled for starting thresholds
+constexpr int kSeedDocs = kSeedGroups * kGroup;
 constexpr int kLits = 12;            // literals per query in the scan's fast mask path
 constexpr uint32_t kKeyNegInf = 0x007FFFFFu;  // order key of -inf
 constexpr uint32_t kKeyPosInf = 0xFF800000u;  // order key of +inf
@@ -158,6 +160,7 @@ struct SeedArgs {
   uint32_t ppad;
   uint32_t n_groups;       // groups sampled
   uint32_t dim;
+  uint32_t* skey;          // [max_list][kSeedDocs] sample score keys (scratch)
   uint32_t* tau;
 };
 

@@ -566,144 +566,6 @@ __device__ __forceinline__ float e4m3_to_f(uint32_t b) {
   return (b & 0x80u) ? -v : v;
 }
 
-// Starting thresholds from a sample (the first groups of the corpus).  One
-// wavefront per query: every lane scores one document of each 64-document
-// word (the tile layout pairs each document chunk with the query chunk that
-// holds the same dimensions), the scores of matching documents go to LDS,
-// and a most-significant-byte-first radix select finds the K'-th largest.
-// The scan accumulates in another order, so the threshold is lowered by
-// twice the FP32 summation bound gamma_d * |q| * max|x| (with 12.5 % slack
-// for the quantised forms' scaled norms): at least K' documents then score
-// at or above it in the scan, so it is a valid lower bound.
-template <int DT, int DPAD>
-__global__ __launch_bounds__(256) void k_seed(SeedArgs a) {
-  constexpr int ES = DT == kF32 ? 4 : DT == kBF16 ? 2 : 1;
-  constexpr int CH = DPAD * ES / 32;
-  constexpr int NS = 4 * kGroup;            // sampled documents at most
-  __shared__ uint32_t s_key[4][NS];
-  __shared__ uint32_t s_hist[4][256];
-  __shared__ uint32_t s_n[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t pos = blockIdx.x * 4u + (uint32_t)wave;
-  if (pos >= *a.n_list || pos >= a.max_list) return;
-  const uint32_t q = a.qlist[pos];
-  const uint32_t kp = a.kp[q];
-  const uint32_t ng = a.n_groups < 4u ? a.n_groups : 4u;
-  if (kp == 0u || kp > ng * (uint32_t)kGroup) return;
-  uint32_t* key = s_key[wave];
-  uint32_t* hist = s_hist[wave];
-  if (lane == 0) s_n[wave] = 0u;
-  __builtin_amdgcn_wave_barrier();
-  const float qs = (DT == kFP8 && a.qscale) ? a.qscale[q] : 1.f;
-  const uint4* qt = (const uint4*)(a.qtiles + (uint64_t)(q / kTile) * (CH * 1024));
-  for (uint32_t g = 0; g < ng; ++g) {
-    for (int w = 0; w < kWords; ++w) {
-      const uint64_t m = a.mw[((uint64_t)g * kWords + w) * a.ppad + pos];
-      if (!m) continue;
-      const uint64_t slot = (uint64_t)g * kGroup + (uint64_t)w * 64 + lane;
-      const uint64_t tile = slot / kTile;
-      const uint32_t r = (uint32_t)(slot % kTile);
-      const uint4* xt = (const uint4*)(a.tiles + tile * (uint64_t)(CH * 1024));
-      float acc = 0.f;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-#pragma unroll 4
-        for (int j = 0; j < CH; ++j) {
-          const uint4 x = xt[j * 64 + h * 32 + r];
-          const uint4 y = qt[j * 64 + h * 32 + (q % kTile)];
-          const uint32_t xv[4] = {x.x, x.y, x.z, x.w}, yv[4] = {y.x, y.y, y.z, y.w};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            if constexpr (DT == kF32) {
-              acc = fmaf(__uint_as_float(xv[e]), __uint_as_float(yv[e]), acc);
-            } else if constexpr (DT == kBF16) {
-              acc = fmaf(__uint_as_float(xv[e] << 16), __uint_as_float(yv[e] << 16), acc);
-              acc = fmaf(__uint_as_float(xv[e] & 0xFFFF0000u), __uint_as_float(yv[e] & 0xFFFF0000u), acc);
-            } else {
-#pragma unroll
-              for (int b = 0; b < 4; ++b)
-                acc = fmaf(e4m3_to_f((xv[e] >> (8 * b)) & 0xFFu), e4m3_to_f((yv[e] >> (8 * b)) & 0xFFu), acc);
-            }
-          }
-        }
-      }
-      if constexpr (DT == kFP8) acc = (acc * qs) * a.xscale[slot];
-      if ((m >> lane) & 1ull) {
-        const uint32_t at = atomicAdd(&s_n[wave], 1u);
-        key[at] = fkey(acc);
-      }
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const uint32_t n = s_n[wave];
-  if (n < kp) return;
-  // radix select of the kp-th largest key, most significant byte first
-  uint32_t prefix = 0u, pmask = 0u, rank = kp;
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    for (int i = lane; i < 256; i += 64) hist[i] = 0u;
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t i = lane; i < n; i += 64) {
-      const uint32_t k = key[i];
-      if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // digit d with (count above d) < rank <= (count at or above d)
-    uint32_t acc = 0u;
-    int d = 255;
-    for (; d > 0; --d) {
-      const uint32_t c = hist[d];
-      if (acc + c >= rank) break;
-      acc += c;
-    }
-    rank -= acc;
-    prefix |= (uint32_t)d << shift;
-    pmask |= 255u << shift;
-    __builtin_amdgcn_wave_barrier();
-  }
-  if (lane == 0) {
-    const float u = 5.9604644775390625e-8f;   // 2^-24
-    const float dd = (float)a.dim;
-    const float gam = dd * u / (1.f - dd * u);
-    const float tol = 2.f * gam * a.qnorm[q] * __uint_as_float(*a.norm_max) * 1.125f + 1e-30f;
-    const float t = key2f(prefix) - tol;
-    atomicMax(a.tau + q, fkey(t));
-  }
-}
-
-#define FR_SEED_CASES(X) \
-  X(kF32, 64) X(kF32, 128) X(kF32, 192) X(kF32, 256) \
-  X(kBF16, 64) X(kBF16, 128) X(kBF16, 192) X(kBF16, 256) \
-  X(kFP8, 64) X(kFP8, 128) X(kFP8, 192) X(kFP8, 256)
-
-hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s) {
-  FR_REQUIRE(a.qlist);
-  FR_REQUIRE(a.n_list);
-  FR_REQUIRE(a.kp);
-  FR_REQUIRE(a.tiles);
-  FR_REQUIRE(a.qtiles);
-  FR_REQUIRE(a.qnorm);
-  FR_REQUIRE(a.norm_max);
-  FR_REQUIRE(a.mw);
-  FR_REQUIRE(a.tau);
-  if (dt == kFP8) {
-    FR_REQUIRE(a.xscale);
-    FR_REQUIRE(a.qscale);
-  }
-  if (a.max_list == 0 || a.n_groups == 0) return hipSuccess;
-#define FR_SEED(D, P)                                                                      \
-  if (dt == D && dpad == P) {                                                              \
-    hipLaunchKernelGGL((k_seed<D, P>), dim3((a.max_list + 3u) / 4u), dim3(256), 0, s, a); \
-    return hipGetLastError();                                                              \
-  }
-  FR_SEED_CASES(FR_SEED)
-#undef FR_SEED
-  return hipErrorInvalidValue;
-}
-
 __global__ void k_zero_work(uint32_t* w) {
   if (threadIdx.x < kXcds) w[threadIdx.x] = 0u;
 }
@@ -882,6 +744,179 @@ __device__ __forceinline__ void read_scales(float4 (&xs)[4], const float* sslot,
   for (int g = 0; g < 4; ++g) xs[g] = s[2 * g];
 }
 
+// Starting thresholds from a sample: the first kSeedGroups groups of the
+// corpus.  Step 1 scores every (sampled document, list position) pair with
+// the scan's own tile product (one wavefront per 32-document tile and
+// 32-position query block, the same instruction sequence as the scan, so
+// the scores match the scan's); step 2 keeps the matching documents of one
+// position and radix-selects its K'-th largest score.  The threshold is
+// still lowered by twice the FP32 summation bound gamma_d * |q| * max|x|
+// (12.5 % slack for the quantised forms' scaled norms), so it stays a lower
+// bound of the K'-th best final score whatever the accumulation order.
+template <int DT, int DPAD>
+__global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
+  constexpr int ES = DT == kF32 ? 4 : DT == kBF16 ? 2 : 1;
+  constexpr int CH = DPAD * ES / 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  const uint32_t n_list = *a.n_list;
+  const uint32_t pos0 = blockIdx.y * (uint32_t)kTile;
+  const uint32_t ng = a.n_groups < (uint32_t)kSeedGroups ? a.n_groups : (uint32_t)kSeedGroups;
+  const uint32_t t = blockIdx.x * 4u + (uint32_t)wave;
+  if (pos0 >= n_list || pos0 >= a.max_list || t >= ng * (uint32_t)(kGroup / kTile)) return;
+  const uint32_t pos = pos0 + (uint32_t)col;
+  const bool qv = pos < n_list && pos < a.max_list;
+  const uint32_t q = qv ? a.qlist[pos] : 0u;
+  uint4 bq[1][CH];
+  const uint4* qp = (const uint4*)(a.qtiles + (uint64_t)(q / kTile) * (CH * 1024)) + half * 32 +
+                    (q % kTile);
+#pragma unroll
+  for (int j = 0; j < CH; ++j) bq[0][j] = qv ? qp[j * 64] : make_uint4(0, 0, 0, 0);
+  f32x16 acc[1];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[0][v] = 0.f;
+  mma_tile<DT, CH, 1>(acc, a.tiles + (uint64_t)t * (CH * 1024), bq, lane);
+  if (!qv) return;
+  const float qs = DT == kFP8 ? a.qscale[q] : 1.f;
+  uint32_t* out = a.skey + (uint64_t)pos * kSeedDocs + (uint64_t)t * kTile;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    uint32_t k4[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float sc = acc[0][4 * g + e];
+      if constexpr (DT == kFP8) sc = (sc * qs) * a.xscale[(uint64_t)t * kTile + acc_row(4 * g + e, half)];
+      k4[e] = fkey(sc);
+    }
+    *(uint4*)(out + 8 * g + 4 * half) = make_uint4(k4[0], k4[1], k4[2], k4[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_seed_select(SeedArgs a) {
+  __shared__ uint32_t s_key[kSeedDocs];
+  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_n, s_digit, s_rank;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint32_t pos = blockIdx.x;
+  if (pos >= *a.n_list || pos >= a.max_list) return;
+  const uint32_t q = a.qlist[pos];
+  const uint32_t kp = a.kp[q];
+  const uint32_t ng = a.n_groups < (uint32_t)kSeedGroups ? a.n_groups : (uint32_t)kSeedGroups;
+  const uint32_t nd = ng * (uint32_t)kGroup;
+  if (kp == 0u || kp > nd) return;
+  if (tid == 0) s_n = 0u;
+  __syncthreads();
+  // 16 documents per thread; key 0 (below every finite score's key) marks
+  // a document that does not match
+  static_assert(kSeedDocs == 256 * 16, "seed sample layout");
+  const uint32_t i0 = (uint32_t)tid * 16u;
+  uint32_t bits = 0u;
+  uint4 kk[4] = {};
+  if (i0 < nd) {
+    bits = (uint32_t)(a.mw[(uint64_t)(i0 / 64u) * a.ppad + pos] >> (i0 % 64u)) & 0xFFFFu;
+    const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * kSeedDocs + i0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) kk[c] = src[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint32_t m = bits >> (4 * c);
+    s_key[i0 + 4 * c + 0] = (m & 1u) ? kk[c].x : 0u;
+    s_key[i0 + 4 * c + 1] = (m & 2u) ? kk[c].y : 0u;
+    s_key[i0 + 4 * c + 2] = (m & 4u) ? kk[c].z : 0u;
+    s_key[i0 + 4 * c + 3] = (m & 8u) ? kk[c].w : 0u;
+  }
+  if (bits) atomicAdd(&s_n, (uint32_t)__builtin_popcount(bits));
+  __syncthreads();
+  if (s_n < kp) return;   // uniform: too few matches in the sample
+  // most-significant-byte-first radix select of the kp-th largest key
+  uint32_t prefix = 0u, pmask = 0u, rank = kp;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    s_hist[tid] = 0u;
+    __syncthreads();
+    for (int i = tid; i < kSeedDocs; i += 256) {
+      const uint32_t k = s_key[i];
+      if (k != 0u && (k & pmask) == prefix) atomicAdd(&s_hist[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      // lane l holds digits 4l..4l+3; suffix sums over lanes find the digit
+      // d with (count above d) < rank <= (count at or above d)
+      uint32_t h[4], c = 0u;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        h[e] = s_hist[4 * lane + e];
+        c += h[e];
+      }
+      uint32_t suf = c;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_down(suf, off, 64);
+        if (lane + off < 64) suf += o;
+      }
+      uint32_t above = suf - c;
+      if (above < rank && rank <= suf) {
+        for (int e = 3; e >= 0; --e) {
+          if (above + h[e] >= rank) {
+            s_digit = 4u * (uint32_t)lane + (uint32_t)e;
+            s_rank = rank - above;
+            break;
+          }
+          above += h[e];
+        }
+      }
+    }
+    __syncthreads();
+    prefix |= s_digit << shift;
+    pmask |= 255u << shift;
+    rank = s_rank;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const float u = 5.9604644775390625e-8f;   // 2^-24
+    const float dd = (float)a.dim;
+    const float gam = dd * u / (1.f - dd * u);
+    const float tol = 2.f * gam * a.qnorm[q] * __uint_as_float(*a.norm_max) * 1.125f + 1e-30f;
+    const float tv = key2f(prefix) - tol;
+    atomicMax(a.tau + q, fkey(tv));
+  }
+}
+
+#define FR_SEED_CASES(X) \
+  X(kF32, 64) X(kF32, 128) X(kF32, 192) X(kF32, 256) \
+  X(kBF16, 64) X(kBF16, 128) X(kBF16, 192) X(kBF16, 256) \
+  X(kFP8, 64) X(kFP8, 128) X(kFP8, 192) X(kFP8, 256)
+
+hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s) {
+  FR_REQUIRE(a.qlist);
+  FR_REQUIRE(a.n_list);
+  FR_REQUIRE(a.kp);
+  FR_REQUIRE(a.tiles);
+  FR_REQUIRE(a.qtiles);
+  FR_REQUIRE(a.qnorm);
+  FR_REQUIRE(a.norm_max);
+  FR_REQUIRE(a.mw);
+  FR_REQUIRE(a.skey);
+  FR_REQUIRE(a.tau);
+  if (dt == kFP8) {
+    FR_REQUIRE(a.xscale);
+    FR_REQUIRE(a.qscale);
+  }
+  if (a.max_list == 0 || a.n_groups == 0) return hipSuccess;
+  const uint32_t ng = a.n_groups < (uint32_t)kSeedGroups ? a.n_groups : (uint32_t)kSeedGroups;
+  const dim3 g1((ng * (kGroup / kTile) + 3u) / 4u, (a.max_list + kTile - 1u) / kTile);
+#define FR_SEED(D, P)                                                  \
+  if (dt == D && dpad == P) {                                          \
+    hipLaunchKernelGGL((k_seed_scores<D, P>), g1, dim3(256), 0, s, a); \
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;   \
+    hipLaunchKernelGGL(k_seed_select, dim3(a.max_list), dim3(256), 0, s, a); \
+    return hipGetLastError();                                          \
+  }
+  FR_SEED_CASES(FR_SEED)
+#undef FR_SEED
+  return hipErrorInvalidValue;
+}
+
 // Literal table of one query (built by the prep kernel): up to kLits term
 // ids and a packed info word (see PrepArgs).  A lane evaluates the CNF of a
 // query over one 64-document word with all literal loads in flight at once.
@@ -955,13 +990,16 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   constexpr int QT = NW * QB * 32;          // queries per work item
   constexpr int LM = QT / 128;              // 1 KB mask loads per word (and per tile)
   constexpr int LT = R::L + LM;             // loader's loads per tile
+  // tiles in flight: the ring's choice, within the 6-bit memory counter
+  constexpr int PD = (R::PD - 1) * LT <= 63 ? R::PD : 63 / LT + 1;
+  constexpr int NS = PD + 1;                // ring slots
   constexpr int SR = 512;                   // staging ring entries per wavefront
   constexpr long long kPeriod = 3000;       // keeper period, shader clocks
   constexpr int RJ = QT / 64;               // queries per keeper lane
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   static_assert(QT <= 256, "staged query index is one byte");
-  __shared__ __attribute__((aligned(16))) uint8_t s_ring[R::NS * R::TB];
-  __shared__ __attribute__((aligned(16))) float s_rscale[DT == kFP8 ? R::NS * kTile : 4];
+  __shared__ __attribute__((aligned(16))) uint8_t s_ring[NS * R::TB];
+  __shared__ __attribute__((aligned(16))) float s_rscale[DT == kFP8 ? NS * kTile : 4];
   // predicate masks of the current and the next group: [group % 2][word][j]
   __shared__ __attribute__((aligned(16))) uint64_t s_mask[2][kWords][QT];
   __shared__ __attribute__((aligned(16))) uint8_t s_msink[LM * 1024];   // target of padding loads
@@ -974,7 +1012,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   __shared__ float s_qiw[QT];
   // ring hand-over: sequence number of the tile in each slot, tiles done
   // per compute wavefront (sequence numbers run on across items)
-  __shared__ uint32_t s_ready[R::NS];
+  __shared__ uint32_t s_ready[NS];
   __shared__ uint32_t s_done[NW];
   __shared__ uint32_t s_fin[NW];            // item number a compute wavefront finished
   // staging rings: entries (score key << 32 | slot) and the query's j;
@@ -1065,18 +1103,18 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       uint32_t issued = 0, published = 0;
       while (published < n_t) {
         bool moved = false;
-        while (issued < n_t && issued - published < (uint32_t)R::PD) {
+        while (issued < n_t && issued - published < (uint32_t)PD) {
           const uint32_t sq = seq0 + issued;
-          if (sq >= (uint32_t)R::NS) {
+          if (sq >= (uint32_t)NS) {
             uint32_t mind = 0xFFFFFFFFu;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
               const uint32_t d = lds_word_ld(&s_done[w]);
               mind = d < mind ? d : mind;
             }
-            if (mind < sq - (uint32_t)R::NS + 1u) break;   // slot still in use
+            if (mind < sq - (uint32_t)NS + 1u) break;   // slot still in use
           }
-          const uint32_t slot = sq % (uint32_t)R::NS;
+          const uint32_t slot = sq % (uint32_t)NS;
           const uint32_t gi = issued >> 5, t = issued & 31u;
           if (t >= 16u && gi + 1u < n_t / 32u) dma_mask(gi + 1u, (int)(t - 16u));
           else dma_pad();
@@ -1086,9 +1124,9 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
           moved = true;
         }
         if (published < issued) {
-          wait_tiles<LT, R::PD>(issued - published - 1u);
+          wait_tiles<LT, PD>(issued - published - 1u);
           const uint32_t sq = seq0 + published;
-          if (lane == 0) lds_word_st(&s_ready[sq % (uint32_t)R::NS], sq);
+          if (lane == 0) lds_word_st(&s_ready[sq % (uint32_t)NS], sq);
           ++published;
           moved = true;
         }
@@ -1332,7 +1370,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   float thr[QB], hlo[QB], hinv[QB], qs[QB];
   bool qv[QB];
   if (wave == 0) {
-    for (int i = lane; i < R::NS; i += 64) s_ready[i] = 0xFFFFFFFFu;
+    for (int i = lane; i < NS; i += 64) s_ready[i] = 0xFFFFFFFFu;
     for (int i = lane; i < NW; i += 64) {
       s_done[i] = 0u;
       s_fin[i] = 0xFFFFFFFFu;
@@ -1401,7 +1439,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       const uint32_t ti0 = (uint32_t)(g - g0) * (kGroup / kTile);   // item-relative tile
       // the group's masks have landed once its first tile is published
       const uint32_t sq0 = seq0 + ti0;
-      while (lds_get(&s_ready[sq0 % (uint32_t)R::NS]) != sq0) __builtin_amdgcn_s_sleep(1);
+      while (lds_get(&s_ready[sq0 % (uint32_t)NS]) != sq0) __builtin_amdgcn_s_sleep(1);
       const int mb = (int)((sq0 >> 5) & 1u);
       // tiles of this group that some query of this wavefront matches
       uint32_t act = 0;
@@ -1420,7 +1458,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       // (if a query of this wavefront matches the tile) score it
       auto body = [&](int t) {
         const uint32_t sq = seq0 + ti0 + (uint32_t)t;
-        const uint32_t rs = sq % (uint32_t)R::NS;
+        const uint32_t rs = sq % (uint32_t)NS;
         // wait until the loader has published the tile
         while (lds_get(&s_ready[rs]) != sq) __builtin_amdgcn_s_sleep(1);
         if (!((act >> t) & 1u)) {
@@ -1455,12 +1493,11 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
           for (int v = 1; v < 16; ++v) mx = fmaxf(mx, s[v]);
           const bool cand = (m32 != 0u) && (mx >= thr[b]);
           if (__ballot(cand)) {
-            uint32_t pm = 0;
-            if (cand) {
-#pragma unroll
-              for (int v = 0; v < 16; ++v)
-                if (((m32 >> acc_row(v, half)) & 1u) && s[v] >= thr[b]) pm |= 1u << v;
-            }
+            // mask bits of the lane's 16 accumulator rows: row 8g + 4 half + i
+            // (= acc_row(4g + i, half)) goes to bit 4g + i
+            const uint32_t mh = cand ? m32 >> (4 * half) : 0u;
+            const uint32_t msel = (mh & 0xFu) | ((mh >> 4) & 0xF0u) | ((mh >> 8) & 0xF00u) |
+                                  ((mh >> 12) & 0xF000u);
             {
               // wave-wide compaction: the v-th survivors of all lanes take
               // consecutive staging slots (this wavefront is the only writer
@@ -1471,7 +1508,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
               uint32_t base = 0;
 #pragma unroll
               for (int v = 0; v < 16; ++v) {
-                const bool on = (pm >> v) & 1u;
+                const bool on = ((msel >> v) & 1u) && s[v] >= thr[b];
                 const uint64_t bal = __ballot(on);
                 if (bal == 0ull) continue;
                 const uint32_t idx = base + __builtin_amdgcn_mbcnt_hi(
@@ -1524,7 +1561,8 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
 // (dtype, padded dim, query blocks per wavefront, wavefronts per workgroup)
 #define FR_SCAN_CASES(X) \
   X(kF32, 64, 1, 4) X(kF32, 128, 1, 4) X(kF32, 192, 1, 4) X(kF32, 256, 1, 4) \
-  X(kBF16, 64, 2, 4) \
+  X(kBF16, 64, 2, 4) X(kF32, 64, 2, 4) X(kF32, 128, 2, 4) X(kBF16, 128, 2, 4) \
+  X(kFP8, 256, 2, 4) \
   X(kBF16, 64, 1, 4) X(kBF16, 128, 1, 4) X(kBF16, 192, 1, 4) X(kBF16, 256, 1, 4) \
   X(kFP8, 64, 1, 4) X(kFP8, 64, 2, 4) X(kFP8, 128, 1, 4) X(kFP8, 128, 2, 4) \
   X(kFP8, 192, 1, 4) X(kFP8, 256, 1, 4)

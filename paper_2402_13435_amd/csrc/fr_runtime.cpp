@@ -93,6 +93,7 @@ struct Workspace {
   unsigned long long* nmatch = nullptr;
   unsigned long long* cand_key = nullptr;
   uint64_t* mw = nullptr;    // predicate masks of the current pass
+  uint32_t* skey = nullptr;  // sample score keys of the starting thresholds
   unsigned long long* sel_key = nullptr;
   uint32_t* sel_slot = nullptr;
   uint32_t* out_ids = nullptr;
@@ -403,6 +404,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sd.ppad = ma.ppad;
   sd.n_groups = n_groups;
   sd.dim = ix->dim;
+  sd.skey = w.skey;
   sd.tau = w.tau;
   FR_HIP(launch_seed(sd, ix->dt, ix->dpad, s));
 
@@ -715,6 +717,7 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(dalloc(&w.hinvw, qm, D));
     FR_ALLOC(dalloc(&w.nmatch, qm, D));
     FR_ALLOC(dalloc(&w.cand_key, (size_t)qm * ix->cand_cap, D));
+    FR_ALLOC(dalloc(&w.skey, (size_t)qm * kSeedDocs, D));
     FR_ALLOC(dalloc(&w.mw, (size_t)(ix->cap / kGroup) * kWords * mask_ppad(ix), D));
     FR_ALLOC(dalloc(&w.sel_key, (size_t)qm * ix->rmax, D));
     FR_ALLOC(dalloc(&w.sel_slot, (size_t)qm * ix->rmax, D));
@@ -936,7 +939,10 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   if (ix->failed) return fail(FR_EDEVICE, "index failed earlier");
   FR_HIP(hipSetDevice(ix->cfg.device));
   const bool dev = flags & FR_DEVICE_PTRS;
-  if (stream && !dev) return fail(FR_EINVAL, "an asynchronous search needs FR_DEVICE_PTRS");
+  const bool async = stream || (flags & FR_ASYNC);
+  if (async && !dev) return fail(FR_EINVAL, "an asynchronous search needs FR_DEVICE_PTRS");
+  if ((flags & FR_GRAPH) && async && !stream)
+    return fail(FR_EINVAL, "FR_GRAPH cannot capture the null stream");
   if (n_q > ix->qmax) return fail(FR_EINVAL, "n_q exceeds max_batch");
   uint32_t n_c = 0, n_l = 0;
   fr_status st = validate_cnf(ix, n_q, cnf, &n_c, &n_l);
@@ -948,7 +954,7 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
     if (k[q] > ix->cfg.k_max) return fail(FR_EINVAL, "k exceeds k_max");
   Workspace* w = acquire_ws(ix, flags & FR_NOWAIT, &st);
   if (!w) return st;
-  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
+  hipStream_t s = async ? (hipStream_t)stream : ix->stream;
   // inputs
   w->h_desc[0] = n_q;
   w->h_desc[1] = n_q;
@@ -1011,9 +1017,6 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
     FR_HIP(hipMemcpyAsync(w->h_count, w->out_count, n_q * 4, hipMemcpyDeviceToHost, s));
     FR_HIP(hipMemcpyAsync(w->h_nmatch, w->out_nmatch, n_q * 8, hipMemcpyDeviceToHost, s));
   }
-  FR_HIP(hipMemcpyAsync(w->h_cnt, w->cnt, n_q * 4, hipMemcpyDeviceToHost, s));
-  FR_HIP(hipMemcpyAsync(w->h_selcnt, w->sel_cnt, n_q * 4, hipMemcpyDeviceToHost, s));
-  FR_HIP(hipMemcpyAsync(w->h_desc_out, w->desc, 16, hipMemcpyDeviceToHost, s));
   FR_HIP(hipEventRecord(w->done, s));
   w->in_flight = true;
   // algorithmic bytes / flops of this batch (for statistics)
@@ -1030,7 +1033,7 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   w->last_nq = n_q;
   ix->last_ws = (size_t)(w - ix->ws.data());
   ix->have_last = true;
-  if (stream) return FR_OK;
+  if (async) return FR_OK;
   FR_HIP(hipEventSynchronize(w->done));
   w->in_flight = false;
   bool failed_q = false;
@@ -1056,6 +1059,12 @@ fr_status fr_stats(fr_index* ix, fr_search_stats* out) {
   if (!ix->have_last) return fail(FR_EINVAL, "no search yet");
   Workspace& w = ix->ws[ix->last_ws];
   if (hipEventSynchronize(w.done) != hipSuccess) return fail(FR_EDEVICE, "event");
+  // per-query counters of that search, still in its workspace (read here
+  // rather than copied back by every search)
+  if (hipMemcpy(w.h_cnt, w.cnt, w.last_nq * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(w.h_selcnt, w.sel_cnt, w.last_nq * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(w.h_desc_out, w.desc, 16, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(FR_EDEVICE, "hipMemcpy");
   fr_search_stats s{};
   s.n_queries = w.last_nq;
   uint64_t cands = 0;

@@ -169,7 +169,7 @@ def test_determinism_and_batch_invariance(mid):
         r = ix.search(one.emb, one, 100)
         assert np.array_equal(r.ids[0], a.ids[q]) and np.array_equal(r.scores[0], a.scores[q])
         assert r.n_match[0] == a.n_match[q]
-    for qbk, nw, g in ((1, 4, 1), (1, 4, 2), (1, 4, 7)):
+    for qbk, nw, g in ((1, 4, 1), (2, 4, 2), (1, 4, 7)):
         ix.set_tiling(qbk, nw, g)
         t = ix.search(qb.emb, qb, 100)
         assert np.array_equal(t.ids, a.ids) and np.array_equal(t.scores, a.scores)
