@@ -325,8 +325,11 @@ hipError_t launch_masks(const MaskArgs& a, uint64_t total, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- prep
+// One wavefront per query: the lanes clear its histogram, lane 0 sets the
+// per-query state and builds the literal table.
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
-  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint32_t q = blockIdx.x * 4u + (threadIdx.x >> 6);
   const uint32_t n_q = *a.n_dev;
   if (blockIdx.x == 0 && threadIdx.x < kXcds) a.work[threadIdx.x] = 0u;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -334,6 +337,9 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     *a.n_list2 = 0u;
   }
   if (q >= n_q || q >= a.max_q) return;
+  uint32_t* h = a.hist + (uint64_t)q * kHist;
+  for (int i = lane; i < kHist; i += 64) h[i] = 0u;
+  if (lane != 0) return;
   const uint32_t k = a.k[q];
   uint32_t kp = k;
   if (a.dt != kF32 && k) {
@@ -352,8 +358,6 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   const float hi = a.qnorm[q] * m * 1.0001f;
   a.hlo[q] = 0.f;
   a.hinvw[q] = (hi > 0.f && isfinite(hi)) ? (float)kNBF / hi : 0.f;
-  uint32_t* h = a.hist + (uint64_t)q * kHist;
-  for (int i = 0; i < kHist; ++i) h[i] = 0u;
   // literal table
   const uint32_t c0 = a.clause_off[q], c1 = a.clause_off[q + 1];
   const uint32_t l0 = c0 < c1 ? a.literal_off[c0] : 0u, l1 = c0 < c1 ? a.literal_off[c1] : 0u;
@@ -399,7 +403,7 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
   FR_REQUIRE(a.terms);
   FR_REQUIRE(a.lit);
   FR_REQUIRE(a.linfo);
-  hipLaunchKernelGGL(k_prep, dim3(grid_for(a.max_q ? a.max_q : 1, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_prep, dim3(grid_for(a.max_q ? a.max_q : 1, 4)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

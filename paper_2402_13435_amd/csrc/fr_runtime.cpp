@@ -71,6 +71,9 @@ struct Workspace {
   uint8_t* qtiles = nullptr;
   float* qscale = nullptr;
   float* qnorm = nullptr;
+  // per-search inputs, one block copied from its pinned twin at once:
+  // [desc 4][k qmax][clause_off qmax+1][literal_off cmax+1][terms lmax]
+  uint32_t* in = nullptr;
   uint32_t* clause_off = nullptr;
   uint32_t* literal_off = nullptr;
   uint32_t* terms = nullptr;
@@ -100,7 +103,8 @@ struct Workspace {
   float* out_scores = nullptr;
   uint32_t* out_count = nullptr;
   unsigned long long* out_nmatch = nullptr;
-  // pinned host staging
+  // pinned host staging (h_in mirrors in)
+  uint32_t* h_in = nullptr;
   float* h_q = nullptr;
   uint32_t* h_co = nullptr;
   uint32_t* h_lo = nullptr;
@@ -123,7 +127,7 @@ struct Workspace {
   // extent / output binding
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  uint64_t gkey[8] = {};
+  uint64_t gkey[9] = {};
   bool in_flight = false;
   uint32_t last_nq = 0;
   double last_alg_bytes = 0, last_alg_flops = 0;
@@ -326,14 +330,19 @@ int pick_gpi(const fr_index* ix, uint32_t n_q, int qt, uint32_t n_groups) {
 }
 
 fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int nw, int gpi,
-                         uint32_t n_groups, bool timing, uint32_t* o_ids, float* o_scores,
-                         uint32_t* o_count, unsigned long long* o_nmatch) {
+                         uint32_t n_groups, bool timing, const float* qsrc, uint32_t* o_ids,
+                         float* o_scores, uint32_t* o_count, unsigned long long* o_nmatch) {
+  // query rows: the workspace's padded copy (host queries), or the caller's
+  // device rows, of which the kernel then writes the padded copy that the
+  // FP32 rescoring reads
   TileRowsArgs ta{};
-  ta.rows = w.qrow;
+  const bool in_place = qsrc != w.qrow;
+  ta.rows = qsrc;
   ta.n = ix->qmax;
   ta.n_dev = w.desc;
-  ta.dim = ix->dpad;
+  ta.dim = in_place ? ix->dim : ix->dpad;
   ta.dpad = ix->dpad;
+  ta.master = (in_place && ix->dt != kF32) ? w.qrow : nullptr;
   ta.dt = ix->dt;
   ta.tiles = w.qtiles;
   ta.scale = w.qscale;
@@ -565,16 +574,17 @@ fr_status validate_cnf(const fr_index* ix, uint32_t n_q, const fr_cnf_batch* cnf
   return FR_OK;
 }
 
-// Copy the CNF batch into a workspace's pinned staging and to the device.
-fr_status stage_cnf(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_q,
-                    const fr_cnf_batch* cnf, uint32_t n_c, uint32_t n_l) {
+// Copy the CNF batch into a workspace's pinned input block, then the block
+// (descriptor, K values and CNF, up to the last term used) to the device in
+// one copy.
+fr_status stage_inputs(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_q,
+                       const fr_cnf_batch* cnf, uint32_t n_c, uint32_t n_l) {
   std::memcpy(w.h_co, cnf->clause_off, (n_q + 1) * 4);
   if (n_c) std::memcpy(w.h_lo, cnf->literal_off, (n_c + 1) * 4);
   else w.h_lo[0] = 0;
   if (n_l) std::memcpy(w.h_terms, cnf->terms, n_l * 4);
-  FR_HIP(hipMemcpyAsync(w.clause_off, w.h_co, (n_q + 1) * 4, hipMemcpyHostToDevice, s));
-  FR_HIP(hipMemcpyAsync(w.literal_off, w.h_lo, (n_c + 1) * 4, hipMemcpyHostToDevice, s));
-  if (n_l) FR_HIP(hipMemcpyAsync(w.terms, w.h_terms, n_l * 4, hipMemcpyHostToDevice, s));
+  const size_t words = (size_t)(w.h_terms - w.h_in) + n_l;
+  FR_HIP(hipMemcpyAsync(w.in, w.h_in, words * 4, hipMemcpyHostToDevice, s));
   return FR_OK;
 }
 
@@ -696,10 +706,19 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(dalloc(&w.qtiles, (size_t)qpad / kTile * tb, D));
     FR_ALLOC(dalloc(&w.qscale, qm, D));
     FR_ALLOC(dalloc(&w.qnorm, qm, D));
-    FR_ALLOC(dalloc(&w.clause_off, qm + 1, D));
-    FR_ALLOC(dalloc(&w.literal_off, ix->cmax + 1, D));
-    FR_ALLOC(dalloc(&w.terms, ix->lmax, D));
-    FR_ALLOC(dalloc(&w.k, qm, D));
+    const size_t n_in = 4 + (size_t)qm + (qm + 1) + (ix->cmax + 1) + ix->lmax;
+    FR_ALLOC(dalloc(&w.in, n_in, D));
+    FR_ALLOC(halloc(&w.h_in, n_in, H));
+    w.desc = w.in;
+    w.k = w.desc + 4;
+    w.clause_off = w.k + qm;
+    w.literal_off = w.clause_off + qm + 1;
+    w.terms = w.literal_off + ix->cmax + 1;
+    w.h_desc = w.h_in;
+    w.h_k = w.h_desc + 4;
+    w.h_co = w.h_k + qm;
+    w.h_lo = w.h_co + qm + 1;
+    w.h_terms = w.h_lo + ix->cmax + 1;
     FR_ALLOC(dalloc(&w.kp, qm, D));
     FR_ALLOC(dalloc(&w.tau, qm, D));
     FR_ALLOC(dalloc(&w.cnt, qm, D));
@@ -711,7 +730,6 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(dalloc(&w.sel_cnt, qm, D));
     FR_ALLOC(dalloc(&w.lit, (size_t)qm * kLits, D));
     FR_ALLOC(dalloc(&w.linfo, qm, D));
-    FR_ALLOC(dalloc(&w.desc, 4, D));
     FR_ALLOC(dalloc(&w.work, kXcds, D));
     FR_ALLOC(dalloc(&w.hlo, qm, D));
     FR_ALLOC(dalloc(&w.hinvw, qm, D));
@@ -726,11 +744,6 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(dalloc(&w.out_count, qm, D));
     FR_ALLOC(dalloc(&w.out_nmatch, qm, D));
     FR_ALLOC(halloc(&w.h_q, (size_t)qm * ix->dpad, H));
-    FR_ALLOC(halloc(&w.h_co, qm + 1, H));
-    FR_ALLOC(halloc(&w.h_lo, ix->cmax + 1, H));
-    FR_ALLOC(halloc(&w.h_terms, ix->lmax, H));
-    FR_ALLOC(halloc(&w.h_k, qm, H));
-    FR_ALLOC(halloc(&w.h_desc, 4, H));
     FR_ALLOC(halloc(&w.h_ids, (size_t)qm * cfg->k_max, H));
     FR_ALLOC(halloc(&w.h_scores, (size_t)qm * cfg->k_max, H));
     FR_ALLOC(halloc(&w.h_count, qm, H));
@@ -960,16 +973,13 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   w->h_desc[1] = n_q;
   w->h_desc[2] = 0;
   w->h_desc[3] = 0;
-  FR_HIP(hipMemcpyAsync(w->desc, w->h_desc, 16, hipMemcpyHostToDevice, s));
   std::memcpy(w->h_k, k, n_q * 4);
-  FR_HIP(hipMemcpyAsync(w->k, w->h_k, n_q * 4, hipMemcpyHostToDevice, s));
-  st = stage_cnf(ix, *w, s, n_q, cnf, n_c, n_l);
+  st = stage_inputs(ix, *w, s, n_q, cnf, n_c, n_l);
   if (st != FR_OK) return st;
   const size_t qbytes = (size_t)ix->dpad * 4;
-  if (dev) {
-    FR_HIP(hipMemcpy2DAsync(w->qrow, qbytes, queries, (size_t)ix->dim * 4, (size_t)ix->dim * 4,
-                            n_q, hipMemcpyDeviceToDevice, s));
-  } else {
+  // device queries are read in place by the query tiling kernel
+  const float* qsrc = dev ? queries : w->qrow;
+  if (!dev) {
     for (uint32_t q = 0; q < n_q; ++q)
       std::memcpy(w->h_q + (size_t)q * ix->dpad, queries + (size_t)q * ix->dim, (size_t)ix->dim * 4);
     FR_HIP(hipMemcpyAsync(w->qrow, w->h_q, n_q * qbytes, hipMemcpyHostToDevice, s));
@@ -987,13 +997,15 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
     // the whole device sequence as one graph, captured once per tiling,
     // corpus extent and output binding; kernels read the batch size from the
     // workspace descriptor, so any batch reuses the graph
-    const uint64_t key[8] = {(uint64_t)qb, (uint64_t)nw, (uint64_t)gpi, n_groups,
+    const uint64_t key[9] = {(uint64_t)qb, (uint64_t)nw, (uint64_t)gpi, n_groups,
                              (uint64_t)(uintptr_t)o_ids, (uint64_t)(uintptr_t)o_scores,
-                             (uint64_t)(uintptr_t)o_count, (uint64_t)(uintptr_t)o_nm};
+                             (uint64_t)(uintptr_t)o_count, (uint64_t)(uintptr_t)o_nm,
+                             (uint64_t)(uintptr_t)qsrc};
     if (!w->gexec || std::memcmp(key, w->gkey, sizeof key) != 0) {
       drop_graph(*w);
       FR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      st = enqueue_search(ix, *w, s, qb, nw, gpi, n_groups, false, o_ids, o_scores, o_count, o_nm);
+      st = enqueue_search(ix, *w, s, qb, nw, gpi, n_groups, false, qsrc, o_ids, o_scores, o_count,
+                          o_nm);
       hipGraph_t g = nullptr;
       const hipError_t ce = hipStreamEndCapture(s, &g);
       if (st != FR_OK) return st;
@@ -1007,7 +1019,8 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
     FR_HIP(hipEventRecord(w->e_scan1, s));
     FR_HIP(hipEventRecord(w->e_end, s));
   } else {
-    st = enqueue_search(ix, *w, s, qb, nw, gpi, n_groups, true, o_ids, o_scores, o_count, o_nm);
+    st = enqueue_search(ix, *w, s, qb, nw, gpi, n_groups, true, qsrc, o_ids, o_scores, o_count,
+                        o_nm);
     if (st != FR_OK) return st;
   }
   const size_t kk = (size_t)n_q * ix->cfg.k_max;
@@ -1133,7 +1146,7 @@ fr_status fr_debug_masks(fr_index* ix, const fr_cnf_batch* cnf, uint64_t* out_bi
   st = wait_all(ix);
   if (st != FR_OK) return st;
   Workspace& w = ix->ws[0];
-  st = stage_cnf(ix, w, ix->stream, n_q, cnf, n_c, n_l);
+  st = stage_inputs(ix, w, ix->stream, n_q, cnf, n_c, n_l);
   if (st != FR_OK) return st;
   // testing entry point: a temporary output buffer
   unsigned long long* d_out = nullptr;
