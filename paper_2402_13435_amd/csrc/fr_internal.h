@@ -16,7 +16,7 @@ constexpr int kHist = kNBC + kNBF;   // u32 counters per query histogram
 constexpr int kXcds = 8;             // work queues (one per XCD)
 constexpr int kSelCap = 8192;        // candidates sorted in LDS by the select kernel
 constexpr int kMaxR = 4096;          // largest K / R handled by select and rescore
-constexpr int kSeedGroups = 4;     // corpus groups sampled for starting thresholds
+constexpr int kSeedGroups = 32;    // corpus groups sampled for starting thresholds
 constexpr int kSeedDocs = kSeedGroups * kGroup;
 constexpr int kLits = 12;            // literals per query in the scan's fast mask path
 constexpr uint32_t kKeyNegInf = 0x007FFFFFu;  // order key of -inf

@@ -810,27 +810,30 @@ __global__ __launch_bounds__(256) void k_seed_select(SeedArgs a) {
   if (kp == 0u || kp > nd) return;
   if (tid == 0) s_n = 0u;
   __syncthreads();
-  // 16 documents per thread; key 0 (below every finite score's key) marks
-  // a document that does not match
-  static_assert(kSeedDocs == 256 * 16, "seed sample layout");
-  const uint32_t i0 = (uint32_t)tid * 16u;
-  uint32_t bits = 0u;
-  uint4 kk[4] = {};
-  if (i0 < nd) {
-    bits = (uint32_t)(a.mw[(uint64_t)(i0 / 64u) * a.ppad + pos] >> (i0 % 64u)) & 0xFFFFu;
-    const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * kSeedDocs + i0);
+  // runs of 16 documents, thread t taking runs t, t + 256, ...; key 0
+  // (below every finite score's key) marks a document that does not match
+  static_assert(kSeedDocs % (256 * 16) == 0, "seed sample layout");
+  uint32_t cnt = 0u;
+  for (uint32_t i0 = (uint32_t)tid * 16u; i0 < (uint32_t)kSeedDocs; i0 += 256u * 16u) {
+    uint32_t bits = 0u;
+    uint4 kk[4] = {};
+    if (i0 < nd) {
+      bits = (uint32_t)(a.mw[(uint64_t)(i0 / 64u) * a.ppad + pos] >> (i0 % 64u)) & 0xFFFFu;
+      const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * kSeedDocs + i0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) kk[c] = src[c];
-  }
+      for (int c = 0; c < 4; ++c) kk[c] = src[c];
+    }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const uint32_t m = bits >> (4 * c);
-    s_key[i0 + 4 * c + 0] = (m & 1u) ? kk[c].x : 0u;
-    s_key[i0 + 4 * c + 1] = (m & 2u) ? kk[c].y : 0u;
-    s_key[i0 + 4 * c + 2] = (m & 4u) ? kk[c].z : 0u;
-    s_key[i0 + 4 * c + 3] = (m & 8u) ? kk[c].w : 0u;
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t m = bits >> (4 * c);
+      s_key[i0 + 4 * c + 0] = (m & 1u) ? kk[c].x : 0u;
+      s_key[i0 + 4 * c + 1] = (m & 2u) ? kk[c].y : 0u;
+      s_key[i0 + 4 * c + 2] = (m & 4u) ? kk[c].z : 0u;
+      s_key[i0 + 4 * c + 3] = (m & 8u) ? kk[c].w : 0u;
+    }
+    cnt += (uint32_t)__builtin_popcount(bits);
   }
-  if (bits) atomicAdd(&s_n, (uint32_t)__builtin_popcount(bits));
+  if (cnt) atomicAdd(&s_n, cnt);
   __syncthreads();
   if (s_n < kp) return;   // uniform: too few matches in the sample
   // most-significant-byte-first radix select of the kp-th largest key

@@ -304,22 +304,23 @@ def test_update_errors_leave_index_unchanged(tiny):
 def test_candidate_overflow_second_pass_and_tie_limit():
     from paper_2402_13435_amd import FrError, Index
     from paper_2402_13435_amd.binding import FR_EUNSUPPORTED
-    # Six predicate groups, every document matches; the query is e_0 and a
-    # document's score is its first coordinate: ~0 in the first four groups
+    # 34 predicate groups, every document matches; the query is e_0 and a
+    # document's score is its first coordinate: ~0 in the first 32 groups
     # (the sample the starting threshold comes from), spread over 0.5..0.99
     # in the last two.  The starting threshold is therefore low, the last
     # groups append far more than the 64-entry buffer holds, and the second
     # pass (from the first pass's histogram) fits.
-    cfg = datagen.scaled(datagen.CONFIGS["tiny"], 6144, 4)
+    n_sample = 32 * 1024
+    cfg = datagen.scaled(datagen.CONFIGS["tiny"], n_sample + 2048, 4)
     rng = np.random.default_rng(7)
-    n, d = 6144, cfg.dim
+    n, d = n_sample + 2048, cfg.dim
     emb = rng.standard_normal((n, d)).astype(np.float32)
     emb[:, 0] = 0.0
     emb /= np.linalg.norm(emb, axis=1, keepdims=True)
     hi = np.linspace(0.5, 0.99, 2048, dtype=np.float64)
     rng.shuffle(hi)
-    emb[4096:] *= np.sqrt(1.0 - hi ** 2)[:, None].astype(np.float32)
-    emb[4096:, 0] = hi.astype(np.float32)
+    emb[n_sample:] *= np.sqrt(1.0 - hi ** 2)[:, None].astype(np.float32)
+    emb[n_sample:, 0] = hi.astype(np.float32)
     ids = np.arange(n, dtype=np.uint32) * 3 + 1
     term_off = np.arange(n + 1, dtype=np.int64)
     terms = np.zeros(n, np.uint32)
