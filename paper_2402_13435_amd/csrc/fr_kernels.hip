@@ -797,7 +797,11 @@ __global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_seed_select(SeedArgs a) {
-  __shared__ uint32_t s_key[kSeedDocs];
+  // The matching documents' keys are compacted into LDS, at most kCap of
+  // them: the K'-th largest of any subset of the matches is still at most
+  // the K'-th largest of all, so a full buffer only loosens the bound.
+  constexpr uint32_t kCap = 16384;
+  __shared__ uint32_t s_key[kCap];
   __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_n, s_digit, s_rank;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -807,43 +811,43 @@ __global__ __launch_bounds__(256) void k_seed_select(SeedArgs a) {
   const uint32_t kp = a.kp[q];
   const uint32_t ng = a.n_groups < (uint32_t)kSeedGroups ? a.n_groups : (uint32_t)kSeedGroups;
   const uint32_t nd = ng * (uint32_t)kGroup;
-  if (kp == 0u || kp > nd) return;
+  if (kp == 0u || kp > nd || kp > kCap) return;
   if (tid == 0) s_n = 0u;
   __syncthreads();
-  // runs of 16 documents, thread t taking runs t, t + 256, ...; key 0
-  // (below every finite score's key) marks a document that does not match
+  // runs of 16 documents, thread t taking runs t, t + 256, ...
   static_assert(kSeedDocs % (256 * 16) == 0, "seed sample layout");
-  uint32_t cnt = 0u;
-  for (uint32_t i0 = (uint32_t)tid * 16u; i0 < (uint32_t)kSeedDocs; i0 += 256u * 16u) {
-    uint32_t bits = 0u;
-    uint4 kk[4] = {};
-    if (i0 < nd) {
-      bits = (uint32_t)(a.mw[(uint64_t)(i0 / 64u) * a.ppad + pos] >> (i0 % 64u)) & 0xFFFFu;
-      const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * kSeedDocs + i0);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) kk[c] = src[c];
-    }
+  for (uint32_t i0 = (uint32_t)tid * 16u; i0 < nd; i0 += 256u * 16u) {
+    const uint32_t bits = (uint32_t)(a.mw[(uint64_t)(i0 / 64u) * a.ppad + pos] >> (i0 % 64u)) & 0xFFFFu;
+    if (!bits) continue;
+    const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * kSeedDocs + i0);
+    uint32_t kk[16];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const uint32_t m = bits >> (4 * c);
-      s_key[i0 + 4 * c + 0] = (m & 1u) ? kk[c].x : 0u;
-      s_key[i0 + 4 * c + 1] = (m & 2u) ? kk[c].y : 0u;
-      s_key[i0 + 4 * c + 2] = (m & 4u) ? kk[c].z : 0u;
-      s_key[i0 + 4 * c + 3] = (m & 8u) ? kk[c].w : 0u;
+      const uint4 v = src[c];
+      kk[4 * c] = v.x;
+      kk[4 * c + 1] = v.y;
+      kk[4 * c + 2] = v.z;
+      kk[4 * c + 3] = v.w;
     }
-    cnt += (uint32_t)__builtin_popcount(bits);
+    uint32_t at = atomicAdd(&s_n, (uint32_t)__builtin_popcount(bits));
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      if ((bits >> e) & 1u) {
+        if (at < kCap) s_key[at] = kk[e];
+        ++at;
+      }
   }
-  if (cnt) atomicAdd(&s_n, cnt);
   __syncthreads();
-  if (s_n < kp) return;   // uniform: too few matches in the sample
+  const uint32_t n = s_n < kCap ? s_n : kCap;
+  if (n < kp) return;   // uniform: too few matches in the sample
   // most-significant-byte-first radix select of the kp-th largest key
   uint32_t prefix = 0u, pmask = 0u, rank = kp;
   for (int shift = 24; shift >= 0; shift -= 8) {
     s_hist[tid] = 0u;
     __syncthreads();
-    for (int i = tid; i < kSeedDocs; i += 256) {
+    for (uint32_t i = (uint32_t)tid; i < n; i += 256u) {
       const uint32_t k = s_key[i];
-      if (k != 0u && (k & pmask) == prefix) atomicAdd(&s_hist[(k >> shift) & 255u], 1u);
+      if ((k & pmask) == prefix) atomicAdd(&s_hist[(k >> shift) & 255u], 1u);
     }
     __syncthreads();
     if (tid < 64) {
