@@ -591,9 +591,11 @@ template <int DT, int CH, int QB>
 __device__ __forceinline__ void mma_tile(f32x16 (&acc)[QB], const uint8_t* slot,
                                          const uint4 (&bq)[QB][CH], int lane) {
   const uint4* p = (const uint4*)slot + lane;
-  constexpr int G = DT == kF32 ? 2 : (CH % 4 == 0 ? 4 : 2);
+  // (FP32 with two query blocks: one chunk at a time, the B operand
+  // already takes half the registers)
+  constexpr int G = DT == kF32 ? (QB >= 2 ? 1 : 2) : (CH % 4 == 0 ? 4 : 2);
   constexpr int NG = CH / G;
-  static_assert(CH % G == 0 && G % 2 == 0, "chunk groups");
+  static_assert(CH % G == 0 && (DT != kFP8 || G % 2 == 0), "chunk groups");
   uint4 buf[2][G];
   auto load = [&](int g, uint4 (&d)[G]) {
 #pragma unroll
