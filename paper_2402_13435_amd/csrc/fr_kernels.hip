@@ -798,7 +798,8 @@ __global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_seed_select(SeedArgs a) {
+constexpr int kSelThreads = 1024;   // one workgroup per query, 16 wavefronts
+__global__ __launch_bounds__(kSelThreads) void k_seed_select(SeedArgs a) {
   // The matching documents' keys are compacted into LDS, at most kCap of
   // them: the K'-th largest of any subset of the matches is still at most
   // the K'-th largest of all, so a full buffer only loosens the bound.
@@ -816,9 +817,8 @@ __global__ __launch_bounds__(256) void k_seed_select(SeedArgs a) {
   if (kp == 0u || kp > nd || kp > kCap) return;
   if (tid == 0) s_n = 0u;
   __syncthreads();
-  // runs of 16 documents, thread t taking runs t, t + 256, ...
-  static_assert(kSeedDocs % (256 * 16) == 0, "seed sample layout");
-  for (uint32_t i0 = (uint32_t)tid * 16u; i0 < nd; i0 += 256u * 16u) {
+  // runs of 16 documents, thread t taking runs t, t + kSelThreads, ...
+  for (uint32_t i0 = (uint32_t)tid * 16u; i0 < nd; i0 += kSelThreads * 16u) {
     const uint32_t bits = (uint32_t)(a.mw[(uint64_t)(i0 / 64u) * a.ppad + pos] >> (i0 % 64u)) & 0xFFFFu;
     if (!bits) continue;
     const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * kSeedDocs + i0);
@@ -845,9 +845,9 @@ __global__ __launch_bounds__(256) void k_seed_select(SeedArgs a) {
   // most-significant-byte-first radix select of the kp-th largest key
   uint32_t prefix = 0u, pmask = 0u, rank = kp;
   for (int shift = 24; shift >= 0; shift -= 8) {
-    s_hist[tid] = 0u;
+    if (tid < 256) s_hist[tid] = 0u;
     __syncthreads();
-    for (uint32_t i = (uint32_t)tid; i < n; i += 256u) {
+    for (uint32_t i = (uint32_t)tid; i < n; i += kSelThreads) {
       const uint32_t k = s_key[i];
       if ((k & pmask) == prefix) atomicAdd(&s_hist[(k >> shift) & 255u], 1u);
     }
@@ -922,7 +922,7 @@ hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s) {
   if (dt == D && dpad == P) {                                          \
     hipLaunchKernelGGL((k_seed_scores<D, P>), g1, dim3(256), 0, s, a); \
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;   \
-    hipLaunchKernelGGL(k_seed_select, dim3(a.max_list), dim3(256), 0, s, a); \
+    hipLaunchKernelGGL(k_seed_select, dim3(a.max_list), dim3(kSelThreads), 0, s, a); \
     return hipGetLastError();                                          \
   }
   FR_SEED_CASES(FR_SEED)
