@@ -264,6 +264,51 @@ def bench_batching(args, torch):
     return 0
 
 
+def bench_qsweep(args, torch):
+    """Roofline curve of the scan: the FP32 workload's corpus (1M x 128,
+    vocab 4,096) searched with batches of 1 .. 1,024 queries in FP32, BF16
+    and FP8 (R=128); per point the scan's algorithmic bytes and flops per
+    second against the HBM and matrix peaks of its dtype, and which binds."""
+    import datagen
+    from paper_2402_13435_amd import Index
+    cfg = datagen.CONFIGS["fp32"]
+    log("generating the fp32 corpus and 1,024 queries")
+    c = datagen.corpus(cfg)
+    big = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms), n_queries=1024)
+    sizes = [int(x) for x in args.q_sizes.split(",")]
+    points = []
+    for dt in ("f32", "bf16", "fp8"):
+        ix = Index(c.n, cfg.dim, cfg.vocab, 100, dtype=dt, rescore_r=128 if dt != "f32" else 0,
+                   max_batch=max(sizes), n_workspaces=2)
+        ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
+        for q in sizes:
+            qb = big.subset(list(range(q)))
+            til = ix.autotune(qb.emb, qb, 100)
+            t = timed_search(torch, ix, qb, 100, args.steps, args.warmup)
+            st = t["stats"]
+            scan_s = t["scan_ms"] * 1e-3
+            gbs = st.alg_bytes / scan_s / 1e9
+            tfs = st.alg_flops / scan_s / 1e12
+            f_hbm = gbs / 8000.0
+            f_mma = tfs / PEAKS[dt]
+            points.append({"dtype": dt, "q": q, "qps": round(t["qps"], 1),
+                           "scan_ms": round(t["scan_ms"], 4),
+                           "search_ms_device": round(t["total_ms"], 4),
+                           "alg_gbs": round(gbs, 1), "alg_tflops": round(tfs, 2),
+                           "frac_hbm": round(f_hbm, 4), "frac_mfma": round(f_mma, 4),
+                           "bound": "hbm" if f_hbm >= f_mma else "mfma",
+                           "tiling": list(til),
+                           "candidates_per_query": round(st.candidates / q, 1)})
+            log(json.dumps(points[-1]))
+        ix.close()
+    line = {"metric": "scan roofline vs queries per pass", "config": {
+        "workload": f"qsweep: {c.n:,} docs x {cfg.dim}-d, vocab {cfg.vocab}, K=100, "
+                    "batches of the first Q of 1,024 queries; BF16/FP8 with R=128",
+        "n_docs": c.n}, "points": points, "data": "synthetic"}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_serving(args, torch):
     """Resident BF16 corpus, Poisson arrivals at fixed rates, continuous
     batching over several workspaces, document inserts and deletes at 1% of
@@ -362,9 +407,11 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--config", default="fp32",
-                    choices=["fp32", "precision", "batching", "serving"],
+                    choices=["fp32", "precision", "batching", "serving", "qsweep"],
                     help="workload (default fp32: the benchmark line)")
     ap.add_argument("--n-docs", type=int, default=0, help="resize the corpus (non-default configs)")
+    ap.add_argument("--q-sizes", default="1,8,32,64,128,256,512,1024",
+                    help="qsweep: queries per pass")
     ap.add_argument("--sample", type=int, default=32, help="oracle-checked queries")
     ap.add_argument("--levels", type=float, nargs="*", default=[0.1, 0.3, 0.5, 0.7, 0.9])
     ap.add_argument("--level-s", type=float, default=10.0)
@@ -394,6 +441,8 @@ def main() -> int:
         return bench_precision(args, torch)
     if args.config == "batching":
         return bench_batching(args, torch)
+    if args.config == "qsweep":
+        return bench_qsweep(args, torch)
     if args.config == "serving":
         return bench_serving(args, torch)
     log("generating the fp32 workload (1M docs x 128, 256 queries)")

@@ -693,14 +693,15 @@ __device__ __forceinline__ void wg_barrier() {
   __asm__ __volatile__("" ::: "memory");
 }
 
-// LDS word access written as inline assembly.  The loader wavefront uses
-// these for its hand-over counters: the compiler cannot tell them apart from
-// the ring its direct-to-LDS loads write, and would otherwise wait for every
-// tile load in flight before each of them.  The load waits for itself only.
-__device__ __forceinline__ uint32_t lds_word_ld(const uint32_t* p) {
+// LDS access written as inline assembly.  The loader wavefront uses these
+// for its hand-over counters: the compiler cannot tell them apart from the
+// ring its direct-to-LDS loads write, and would otherwise wait for every
+// tile load in flight before each of them.  The read waits for itself only
+// (four consecutive 16-byte aligned words in one read).
+__device__ __forceinline__ uint4 lds_quad_ld(const uint32_t* p) {
   const uint32_t addr = (uint32_t)(size_t)(const __attribute__((address_space(3))) uint32_t*)p;
-  uint32_t v;
-  __asm__ __volatile__("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(addr) : "memory");
+  uint4 v;
+  __asm__ __volatile__("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(addr) : "memory");
   return v;
 }
 __device__ __forceinline__ void lds_word_st(uint32_t* p, uint32_t v) {
@@ -1011,6 +1012,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   constexpr int RJ = QT / 64;               // queries per keeper lane
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   static_assert(QT <= 256, "staged query index is one byte");
+  static_assert(NW % 4 == 0, "done counters are read four at a time");
   __shared__ __attribute__((aligned(16))) uint8_t s_ring[NS * R::TB];
   __shared__ __attribute__((aligned(16))) float s_rscale[DT == kFP8 ? NS * kTile : 4];
   // predicate masks of the current and the next group: [group % 2][word][j]
@@ -1026,7 +1028,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   // ring hand-over: sequence number of the tile in each slot, tiles done
   // per compute wavefront (sequence numbers run on across items)
   __shared__ uint32_t s_ready[NS];
-  __shared__ uint32_t s_done[NW];
+  __shared__ __attribute__((aligned(16))) uint32_t s_done[NW];
   __shared__ uint32_t s_fin[NW];            // item number a compute wavefront finished
   // staging rings: entries (score key << 32 | slot) and the query's j;
   // head written by the compute wavefront, tail by the keeper
@@ -1078,7 +1080,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     uint32_t seq0 = 0;                                // first tile of the item
     for (;;) {
       wg_barrier();
-      const uint32_t item = s_item;
+      const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform
       wg_barrier();
       if (item >= my_items) break;
       uint64_t g0, g1;
@@ -1103,10 +1105,14 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
                                                ((uint8_t*)&s_mask[buf][w][0] + 1024 * k),
                                            16, 0, 0);
       };
+      // (padding loads of different workgroups read different kilobytes of
+      // the mask buffer, which holds at least 16 x 256 words, so that no
+      // single line is read by every CU at every tile)
+      const uint64_t* pad_src = a.mw + (uint64_t)(blockIdx.x % 32u) * 128u + 2u * lane;
       auto dma_pad = [&]() {
 #pragma unroll
         for (int k = 0; k < LM; ++k)
-          __builtin_amdgcn_global_load_lds((const void*)(a.mw + 2u * lane),
+          __builtin_amdgcn_global_load_lds((const void*)pad_src,
                                            (__attribute__((address_space(3))) void*)
                                                (s_msink + 1024 * k),
                                            16, 0, 0);
@@ -1114,17 +1120,21 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       for (int w = 0; w < kWords; ++w) dma_mask(0u, w);
       wg_barrier();                                   // set-up
       uint32_t issued = 0, published = 0;
+      // least done-counter over the compute wavefronts as last read: the
+      // counters only grow, so a slot it shows free is free
+      uint32_t mind = 0;
       while (published < n_t) {
         bool moved = false;
         while (issued < n_t && issued - published < (uint32_t)PD) {
           const uint32_t sq = seq0 + issued;
-          if (sq >= (uint32_t)NS) {
-            uint32_t mind = 0xFFFFFFFFu;
+          if (sq >= (uint32_t)NS && mind < sq - (uint32_t)NS + 1u) {
+            uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-              const uint32_t d = lds_word_ld(&s_done[w]);
-              mind = d < mind ? d : mind;
+            for (int w = 0; w < NW; w += 4) {
+              const uint4 d = lds_quad_ld(&s_done[w]);
+              m = min(m, min(min(d.x, d.y), min(d.z, d.w)));
             }
+            mind = __builtin_amdgcn_readfirstlane(m);
             if (mind < sq - (uint32_t)NS + 1u) break;   // slot still in use
           }
           const uint32_t slot = sq % (uint32_t)NS;
@@ -1331,7 +1341,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     uint32_t item_no = 0;
     for (;;) {
       wg_barrier();
-      const uint32_t item = s_item;
+      const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform
       wg_barrier();
       if (item >= my_items) break;
       wg_barrier();                                   // set-up: s_qg, s_thr valid
@@ -1435,7 +1445,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   for (;;) {
     if (tid == 0) s_item = atomicAdd(a.work + xcd, 1u);
     wg_barrier();
-    const uint32_t item = s_item;
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform
     wg_barrier();
     if (item >= my_items) break;
     const uint32_t qt = item % n_qtiles;
@@ -1610,6 +1620,8 @@ hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int 
     FR_REQUIRE(a.qscale);
   }
   if (a.gpi < 1 || n_wg < 1) return hipErrorInvalidValue;
+  // the loader's padding loads read the first 4096 words of the masks
+  if (a.ppad < 256u || a.ppad % 256u) return hipErrorInvalidValue;
 #define FR_LAUNCH(D, P, Q, W)                                                          \
   if (dt == D && dpad == P && qb == Q && nw == W) {                                    \
     hipLaunchKernelGGL((k_scan<D, P, Q, W>), dim3(n_wg), dim3((W + 2) * 64), 0, s, a); \
