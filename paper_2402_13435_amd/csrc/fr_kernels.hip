@@ -1062,9 +1062,11 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  // LDS word written by another wavefront of the workgroup
+  // LDS word written by another wavefront of the workgroup; the hand-over
+  // counters are one value for the whole wavefront, so the result is made
+  // wave-uniform (scalar loop control in the waits)
   auto lds_get = [](const uint32_t* p) -> uint32_t {
-    return __atomic_load_n(p, __ATOMIC_RELAXED);
+    return __builtin_amdgcn_readfirstlane(__atomic_load_n(p, __ATOMIC_RELAXED));
   };
   auto lds_put = [](uint32_t* p, uint32_t v) {
     __asm__ __volatile__("" ::: "memory");     // earlier LDS accesses first
