@@ -361,6 +361,20 @@ def test_device_pointers_and_stream(tiny):
     assert np.array_equal(out.ids.cpu().numpy().view(np.uint32), host.ids)
     assert np.array_equal(out.scores.cpu().numpy(), host.scores)
     assert np.array_equal(out.n_match.cpu().numpy().astype(np.uint64), host.n_match)
+    # the null (default) stream: enqueued asynchronously (FR_ASYNC), same result
+    d = torch.cuda.current_stream()
+    assert d.cuda_stream == 0
+    out2 = ix.search(q, qb, 10, stream=d)
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.ids.cpu().numpy().view(np.uint32), host.ids)
+    assert np.array_equal(out2.scores.cpu().numpy(), host.scores)
+    # a graph cannot be captured on the null stream
+    from paper_2402_13435_amd import FrError
+    from paper_2402_13435_amd.binding import FR_EINVAL
+    with pytest.raises(FrError) as e:
+        ix.search(q, qb, 10, stream=d, graph=True)
+    assert e.value.status == FR_EINVAL
+    ix.close()
 
 
 def test_graph_replays_match_eager(mid):
