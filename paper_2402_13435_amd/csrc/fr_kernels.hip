@@ -1407,15 +1407,32 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   uint32_t item_no = 0;
   uint32_t shead = 0;           // this wavefront's staging head (it is the only writer)
 
+  // Query-block sharing: when the query tile fills only nb of the NW
+  // wavefronts' blocks (a small batch) and nb divides NW, wavefront w takes
+  // block w % nb and the tiles t with t % (NW / nb) == w / nb, so that every
+  // wavefront does matrix work; each (query, tile) pair is still scored once.
+  int bw = wave;                // block of queries this wavefront holds
+  uint32_t tstride = 1, tslot = 0;
   auto my_pos = [&](uint32_t qt, int b) -> uint32_t {
-    return qt * QT + (uint32_t)((wave * QB + b) * 32 + col);
+    return qt * QT + (uint32_t)((bw * QB + b) * 32 + col);
   };
-  auto my_j = [&](int b) -> int { return (wave * QB + b) * 32 + col; };
+  auto my_j = [&](int b) -> int { return (bw * QB + b) * 32 + col; };
   // mask word w of this lane's query in block b, group buffer mb
   auto smask = [&](int mb, int b, int w) -> uint64_t {
-    return s_mask[mb][w][(wave * QB + b) * 32 + col];
+    return s_mask[mb][w][(bw * QB + b) * 32 + col];
   };
   auto load_queries = [&](uint32_t qt) {
+    const uint32_t valid = min((uint32_t)QT, n_list - qt * (uint32_t)QT);
+    const uint32_t nb = (valid + 32u * QB - 1u) / (32u * QB);
+    if (nb < (uint32_t)NW && (uint32_t)NW % nb == 0u) {
+      bw = wave % (int)nb;
+      tstride = (uint32_t)NW / nb;
+      tslot = (uint32_t)wave / nb;
+    } else {
+      bw = wave;
+      tstride = 1;
+      tslot = 0;
+    }
 #pragma unroll
     for (int b = 0; b < QB; ++b) {
       const uint32_t pos = my_pos(qt, b);
@@ -1428,12 +1445,15 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       qs[b] = (DT == kFP8 && qv[b]) ? a.qscale[q] : 1.f;
       thr[b] = (qv[b] && kp[b]) ? key2f(ld_relaxed(a.tau + q)) : INFINITY;
       if (half == 0) {
-        const int j = my_j(b);
-        s_qg[j] = (qv[b] && kp[b]) ? q : kNone;
-        s_qkp[j] = kp[b];
-        s_qlo[j] = hlo[b];
-        s_qiw[j] = hinv[b];
-        s_thr[j] = thr[b];
+        // every wavefront writes the state of its own block: the block it
+        // holds, or (when it shares another block) an unused one
+        const int j = (wave * QB + b) * 32 + col;
+        const bool own = bw == wave;
+        s_qg[j] = (own && qv[b] && kp[b]) ? q : kNone;
+        s_qkp[j] = own ? kp[b] : 0u;
+        s_qlo[j] = own ? hlo[b] : 0.f;
+        s_qiw[j] = own ? hinv[b] : 0.f;
+        s_thr[j] = own ? thr[b] : INFINITY;
       }
       const uint4* p = (const uint4*)(a.qtiles + (uint64_t)(q / kTile) * (CH * 1024)) +
                        half * 32 + (q % kTile);
@@ -1486,7 +1506,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
         const uint32_t rs = sq % (uint32_t)NS;
         // wait until the loader has published the tile
         while (lds_get(&s_ready[rs]) != sq) __builtin_amdgcn_s_sleep(1);
-        if (!((act >> t) & 1u)) {
+        if (!((act >> t) & 1u) || (uint32_t)t % tstride != tslot) {
           lds_put(&s_done[wave], sq + 1u);
           return;
         }
