@@ -16,8 +16,10 @@ constexpr int kHist = kNBC + kNBF;   // u32 counters per query histogram
 constexpr int kXcds = 8;             // work queues (one per XCD)
 constexpr int kSelCap = 8192;        // candidates sorted in LDS by the select kernel
 constexpr int kMaxR = 4096;          // largest K / R handled by select and rescore
-constexpr int kSeedGroups = 32;    // corpus groups sampled for starting thresholds
-constexpr int kSeedDocs = kSeedGroups * kGroup;
+// corpus groups sampled for starting thresholds: FP32 scores cost 16x the
+// matrix time of BF16 ones, so the quantised forms sample more
+constexpr int kSeedGroupsF32 = 32;
+constexpr int kSeedGroupsLow = 64;
 constexpr int kLits = 12;            // literals per query in the scan's fast mask path
 constexpr uint32_t kKeyNegInf = 0x007FFFFFu;  // order key of -inf
 constexpr uint32_t kKeyPosInf = 0xFF800000u;  // order key of +inf
@@ -158,9 +160,10 @@ struct SeedArgs {
   const uint32_t* norm_max;
   const uint64_t* mw;      // the pass's masks (see MaskWordArgs)
   uint32_t ppad;
-  uint32_t n_groups;       // groups sampled
+  uint32_t n_groups;       // groups sampled (the first n_groups of the corpus)
   uint32_t dim;
-  uint32_t* skey;          // [max_list][kSeedDocs] sample score keys (scratch)
+  uint32_t* skey;          // [max_list][row] sample score keys (scratch)
+  uint32_t row;            // skey row stride, >= n_groups * kGroup
   uint32_t* tau;
 };
 

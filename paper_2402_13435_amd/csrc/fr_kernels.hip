@@ -751,7 +751,7 @@ __device__ __forceinline__ void read_scales(float4 (&xs)[4], const float* sslot,
   for (int g = 0; g < 4; ++g) xs[g] = s[2 * g];
 }
 
-// Starting thresholds from a sample: the first kSeedGroups groups of the
+// Starting thresholds from a sample: the first a.n_groups groups of the
 // corpus.  Step 1 scores every (sampled document, list position) pair with
 // the scan's own tile product (one wavefront per 32-document tile and
 // 32-position query block, the same instruction sequence as the scan, so
@@ -768,7 +768,7 @@ __global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
   const int col = lane & 31, half = lane >> 5;
   const uint32_t n_list = *a.n_list;
   const uint32_t pos0 = blockIdx.y * (uint32_t)kTile;
-  const uint32_t ng = a.n_groups < (uint32_t)kSeedGroups ? a.n_groups : (uint32_t)kSeedGroups;
+  const uint32_t ng = a.n_groups;
   const uint32_t t = blockIdx.x * 4u + (uint32_t)wave;
   if (pos0 >= n_list || pos0 >= a.max_list || t >= ng * (uint32_t)(kGroup / kTile)) return;
   const uint32_t pos = pos0 + (uint32_t)col;
@@ -785,7 +785,7 @@ __global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
   mma_tile<DT, CH, 1>(acc, a.tiles + (uint64_t)t * (CH * 1024), bq, lane);
   if (!qv) return;
   const float qs = DT == kFP8 ? a.qscale[q] : 1.f;
-  uint32_t* out = a.skey + (uint64_t)pos * kSeedDocs + (uint64_t)t * kTile;
+  uint32_t* out = a.skey + (uint64_t)pos * a.row + (uint64_t)t * kTile;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     uint32_t k4[4];
@@ -813,8 +813,7 @@ __global__ __launch_bounds__(kSelThreads) void k_seed_select(SeedArgs a) {
   if (pos >= *a.n_list || pos >= a.max_list) return;
   const uint32_t q = a.qlist[pos];
   const uint32_t kp = a.kp[q];
-  const uint32_t ng = a.n_groups < (uint32_t)kSeedGroups ? a.n_groups : (uint32_t)kSeedGroups;
-  const uint32_t nd = ng * (uint32_t)kGroup;
+  const uint32_t nd = a.n_groups * (uint32_t)kGroup;
   if (kp == 0u || kp > nd || kp > kCap) return;
   if (tid == 0) s_n = 0u;
   __syncthreads();
@@ -822,7 +821,7 @@ __global__ __launch_bounds__(kSelThreads) void k_seed_select(SeedArgs a) {
   for (uint32_t i0 = (uint32_t)tid * 16u; i0 < nd; i0 += kSelThreads * 16u) {
     const uint32_t bits = (uint32_t)(a.mw[(uint64_t)(i0 / 64u) * a.ppad + pos] >> (i0 % 64u)) & 0xFFFFu;
     if (!bits) continue;
-    const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * kSeedDocs + i0);
+    const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * a.row + i0);
     uint32_t kk[16];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -917,7 +916,8 @@ hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s) {
     FR_REQUIRE(a.qscale);
   }
   if (a.max_list == 0 || a.n_groups == 0) return hipSuccess;
-  const uint32_t ng = a.n_groups < (uint32_t)kSeedGroups ? a.n_groups : (uint32_t)kSeedGroups;
+  if ((uint64_t)a.n_groups * kGroup > a.row || a.row % 16u) return hipErrorInvalidValue;
+  const uint32_t ng = a.n_groups;
   const dim3 g1((ng * (kGroup / kTile) + 3u) / 4u, (a.max_list + kTile - 1u) / kTile);
 #define FR_SEED(D, P)                                                  \
   if (dt == D && dpad == P) {                                          \

@@ -143,6 +143,7 @@ struct fr_index {
   uint32_t r = 0, r_min = 0;
   uint32_t cand_cap = 0;
   uint32_t qmax = 0, cmax = 0, lmax = 0;
+  uint32_t seed_groups = 0;   // corpus groups sampled for starting thresholds
   int n_cu = 0, n_wg = 0;
   int qb = 0, nw = 0, gpi = 0;   // 0: chosen per batch
   hipStream_t stream = nullptr;
@@ -411,7 +412,8 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sd.norm_max = ix->norm_max;
   sd.mw = w.mw;
   sd.ppad = ma.ppad;
-  sd.n_groups = n_groups;
+  sd.n_groups = std::min(n_groups, ix->seed_groups);
+  sd.row = ix->seed_groups * kGroup;
   sd.dim = ix->dim;
   sd.skey = w.skey;
   sd.tau = w.tau;
@@ -648,6 +650,7 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   ix->r_min = cfg->rescore_min ? std::min(cfg->rescore_min, ix->r) : ix->r;
   ix->rmax = ix->dt == kF32 ? cfg->k_max : ix->r;
   ix->qmax = cfg->max_batch ? cfg->max_batch : 1024;
+  ix->seed_groups = ix->dt == kF32 ? kSeedGroupsF32 : kSeedGroupsLow;
   if (ix->qmax > 65536) return fail(FR_EINVAL, "max_batch must be <= 65536");
   ix->cmax = cfg->max_clauses ? cfg->max_clauses : 8 * ix->qmax;
   ix->lmax = cfg->max_literals ? cfg->max_literals : 32 * ix->qmax;
@@ -735,7 +738,7 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(dalloc(&w.hinvw, qm, D));
     FR_ALLOC(dalloc(&w.nmatch, qm, D));
     FR_ALLOC(dalloc(&w.cand_key, (size_t)qm * ix->cand_cap, D));
-    FR_ALLOC(dalloc(&w.skey, (size_t)qm * kSeedDocs, D));
+    FR_ALLOC(dalloc(&w.skey, (size_t)qm * ix->seed_groups * kGroup, D));
     FR_ALLOC(dalloc(&w.mw, (size_t)(ix->cap / kGroup) * kWords * mask_ppad(ix), D));
     FR_ALLOC(dalloc(&w.sel_key, (size_t)qm * ix->rmax, D));
     FR_ALLOC(dalloc(&w.sel_slot, (size_t)qm * ix->rmax, D));
