@@ -169,6 +169,16 @@ def test_determinism_and_batch_invariance(mid):
         r = ix.search(one.emb, one, 100)
         assert np.array_equal(r.ids[0], a.ids[q]) and np.array_equal(r.scores[0], a.scores[q])
         assert r.n_match[0] == a.n_match[q]
+    # batches that fill 2 and 3 of the 4 compute wavefronts' query blocks
+    # (the first shares blocks between wavefronts, the second does not)
+    for n in (40, 70):
+        idx = list(range(100, 100 + n))
+        sub = qb.subset(idx)
+        ix.set_tiling(1, 4, 0)
+        r = ix.search(sub.emb, sub, 100)
+        ix.set_tiling(0, 0, 0)
+        assert np.array_equal(r.ids, a.ids[idx]) and np.array_equal(r.scores, a.scores[idx])
+        assert np.array_equal(r.n_match, a.n_match[idx])
     for qbk, nw, g in ((1, 4, 1), (2, 4, 2), (1, 4, 7)):
         ix.set_tiling(qbk, nw, g)
         t = ix.search(qb.emb, qb, 100)
