@@ -509,7 +509,7 @@ def main() -> int:
         forms = {}
         for dt in ("bf16", "fp8"):
             tried = []
-            for r_depth in ((128, 256, 512, 1024) if oracle_res else (1024,)):
+            for r_depth in ((100, 128, 256, 512, 1024) if oracle_res else (1024,)):
                 log(f"{dt} form, R={r_depth}")
                 r = run_form(torch, c, qb, k, dt, args.steps, args.warmup, rescore_r=r_depth)
                 f = {"qps": round(n_q * args.steps / r["elapsed"], 1),
