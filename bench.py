@@ -73,9 +73,25 @@ def cpu_baseline(c, qb, k: int, budget_s: float):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": len(done) / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(done)} of {qb.n} queries (random order), full corpus, "
-                      f"{dt:.1f} s single-threaded NumPy FP64; posting lists built untimed"}, results
+    single = {"value": len(done) / dt, "cores": 1, "seconds": round(dt, 2)}
+    # the same queries again, one oracle call per query on a thread pool over
+    # the host cores (NumPy releases the GIL in the scoring and sorting)
+    from concurrent.futures import ThreadPoolExecutor
+    try:
+        n_cpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n_cpu = os.cpu_count() or 1
+    workers = max(1, min(16, n_cpu))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(workers) as ex:
+        again = list(ex.map(lambda q: o.search_one(qb.emb[q], qb.cnf(q), k), done))
+    dtp = time.perf_counter() - t0
+    assert all(np.array_equal(r.ids, results[q].ids) for r, q in zip(again, done))
+    return {"value": len(done) / dtp, "unit": "queries/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(done)} of {qb.n} queries (random order), full corpus, NumPy FP64, "
+                      f"one query per task on {workers} threads: {dtp:.1f} s "
+                      f"(single thread: {dt:.1f} s); posting lists built untimed",
+            "single_thread": single}, results
 
 
 def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None, blocks=1):
