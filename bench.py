@@ -441,11 +441,12 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run an elementwise kernel that reads and "
                          "writes 1 GiB (known traffic, to scale HBM counter readings)")
-    # The FP32 workload's tiling is fixed: 2 blocks of 32 queries per
-    # wavefront and 4 groups per work item (245 items for 256 workgroups)
-    # was the fastest of a sweep, and autotuning picks between near-equal
-    # tilings by run-to-run noise.
-    ap.add_argument("--tiling", default="2,4,4",
+    # The FP32 workload's tiling is fixed: 8 compute wavefronts of one
+    # 32-query block each (two per SIMD, so one's epilogue overlaps the
+    # other's matrix work) and 4 groups per work item (245 items for 256
+    # workgroups) was the fastest of a sweep; autotuning picks between
+    # near-equal tilings by run-to-run noise.
+    ap.add_argument("--tiling", default="1,8,4",
                     help="query_blocks,waves,groups_per_item for the FP32 path, or 'auto'")
     args = ap.parse_args()
     if args.gpus != 1:

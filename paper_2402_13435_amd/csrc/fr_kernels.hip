@@ -1007,7 +1007,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   // tiles in flight: the ring's choice, within the 6-bit memory counter
   constexpr int PD = (R::PD - 1) * LT <= 63 ? R::PD : 63 / LT + 1;
   constexpr int NS = PD + 1;                // ring slots
-  constexpr int SR = 512;                   // staging ring entries per wavefront
+  constexpr int SR = NW > 4 ? 256 : 512;    // staging ring entries per wavefront
   constexpr long long kPeriod = 3000;       // keeper period, shader clocks
   constexpr int RJ = QT / 64;               // queries per keeper lane
   constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -1610,7 +1610,8 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   X(kFP8, 256, 2, 4) \
   X(kBF16, 64, 1, 4) X(kBF16, 128, 1, 4) X(kBF16, 192, 1, 4) X(kBF16, 256, 1, 4) \
   X(kFP8, 64, 1, 4) X(kFP8, 64, 2, 4) X(kFP8, 128, 1, 4) X(kFP8, 128, 2, 4) \
-  X(kFP8, 192, 1, 4) X(kFP8, 256, 1, 4)
+  X(kFP8, 192, 1, 4) X(kFP8, 256, 1, 4) \
+  X(kF32, 128, 1, 8) X(kBF16, 128, 1, 8) X(kFP8, 128, 1, 8)
 
 bool scan_supported(int dt, int dpad, int qb, int nw) {
 #define FR_SUP(D, P, Q, W) if (dt == D && dpad == P && qb == Q && nw == W) return true;

@@ -179,7 +179,7 @@ def test_determinism_and_batch_invariance(mid):
         ix.set_tiling(0, 0, 0)
         assert np.array_equal(r.ids, a.ids[idx]) and np.array_equal(r.scores, a.scores[idx])
         assert np.array_equal(r.n_match, a.n_match[idx])
-    for qbk, nw, g in ((1, 4, 1), (2, 4, 2), (1, 4, 7)):
+    for qbk, nw, g in ((1, 4, 1), (2, 4, 2), (1, 4, 7), (1, 8, 3)):
         ix.set_tiling(qbk, nw, g)
         t = ix.search(qb.emb, qb, 100)
         assert np.array_equal(t.ids, a.ids) and np.array_equal(t.scores, a.scores)
