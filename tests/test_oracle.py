@@ -339,3 +339,118 @@ def test_approx_scores_unit_query_bf16(tiny):
     e[5] = 1.0
     got = ix.approx_scores(e, rows, "bf16")
     assert np.array_equal(got, quant.bf16_round(c.emb[:, 5]).astype(np.float64))
+
+
+def _torch_e4m3(v: np.ndarray) -> np.ndarray:
+    """Decoded E4M3FN values of FP32 inputs, by PyTorch's own cast (independent
+    of ``oracle.quant``, which emulates the format by nearest grid point)."""
+    torch = pytest.importorskip("torch")
+    if not hasattr(torch, "float8_e4m3fn"):
+        pytest.skip("torch without float8_e4m3fn")
+    t = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32))
+    return t.to(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+
+
+def _fp8_expected(x: np.ndarray):
+    """(decoded codes, FP32 scale) per row: scale = fl32(amax / 448), codes
+    from fl32(x * fl32(448 / amax)) through PyTorch's E4M3FN cast."""
+    x = np.asarray(x, dtype=np.float32)
+    amax = np.abs(x).max(axis=1).astype(np.float32)
+    nz = amax > 0
+    inv = np.where(nz, np.float32(448.0) / np.where(nz, amax, np.float32(1)),
+                   np.float32(1)).astype(np.float32)
+    scale = np.where(nz, amax / np.float32(448.0), np.float32(1)).astype(np.float32)
+    return _torch_e4m3((x * inv[:, None]).astype(np.float32)), scale
+
+
+def test_approx_scores_unit_query_fp8(tiny):
+    """q = e_k quantises to 448 at k (scale fl32(1/448)), so the first-pass
+    score of row i is decode(code_ik) * s_i * 448 * fl32(1/448): a dropped or
+    swapped scale, or a wrong column, fails this."""
+    c, qb, ix = tiny
+    rows = np.arange(0, c.n, 7)
+    dec, xs = _fp8_expected(c.emb[rows])
+    qscale = float(np.float32(1.0) / np.float32(448.0))
+    for k in (0, 5, 63):
+        e = np.zeros(c.cfg.dim, dtype=np.float32)
+        e[k] = 1.0
+        got = ix.approx_scores(e, rows, "fp8")
+        want = dec[:, k] * 448.0 * qscale * xs.astype(np.float64)
+        assert np.allclose(got, want, rtol=4 * 2.0 ** -53, atol=0), k
+        # a negative, scaled unit query: the same codes, sign flipped
+        e[k] = -3.0
+        got = ix.approx_scores(e, rows, "fp8")
+        want = -dec[:, k] * 448.0 * float(np.float32(3.0) / np.float32(448.0)) * xs
+        assert np.allclose(got, want, rtol=4 * 2.0 ** -53, atol=0), k
+
+
+def test_approx_scores_fp8_brute_force(tiny):
+    """Random queries and rows: math.fsum of the products of the decoded
+    codes (PyTorch's cast), times both FP32 scales."""
+    c, qb, ix = tiny
+    rows = np.arange(3, c.n, 997)
+    dec, xs = _fp8_expected(c.emb[rows])
+    for q in range(4):
+        qd, qs = _fp8_expected(qb.emb[q][None, :])
+        got = ix.approx_scores(qb.emb[q], rows, "fp8")
+        for i, r in enumerate(rows):
+            dot = math.fsum(float(a) * float(b) for a, b in zip(dec[i], qd[0]))
+            want = dot * float(qs[0]) * float(xs[i])
+            bound = math.fsum(abs(float(a) * float(b)) for a, b in zip(dec[i], qd[0]))
+            err = 64 * 2.0 ** -53 * bound * float(qs[0]) * float(xs[i]) + 4 * 2.0 ** -53 * abs(want)
+            assert abs(got[i] - want) <= err, (q, r)
+
+
+def test_approx_scores_bf16_brute_force(tiny):
+    """BF16 first pass: fsum of the products of PyTorch-rounded operands."""
+    torch = pytest.importorskip("torch")
+    c, qb, ix = tiny
+    rows = np.arange(11, c.n, 1013)
+    xb = torch.from_numpy(c.emb[rows]).to(torch.bfloat16).double().numpy()
+    for q in range(4):
+        qbf = torch.from_numpy(qb.emb[q]).to(torch.bfloat16).double().numpy()
+        got = ix.approx_scores(qb.emb[q], rows, "bf16")
+        for i in range(len(rows)):
+            want = math.fsum(float(a) * float(b) for a, b in zip(xb[i], qbf))
+            bound = math.fsum(abs(float(a) * float(b)) for a, b in zip(xb[i], qbf))
+            assert abs(got[i] - want) <= 64 * 2.0 ** -53 * bound, (q, i)
+
+
+def test_update_inserts_against_set_brute_force():
+    """Replay the update log on a pure-Python state (id -> (row, term set))
+    built from the initial corpus and the log alone, never from the oracle's
+    arrays, and compare every query's brute-force result (sets + fsum) with
+    the oracle's.  An inserted row attached to the wrong id, or a term list
+    shifted between documents, changes some result."""
+    cfg = datagen.scaled(datagen.CONFIGS["tiny"], 2000, 8)
+    c = datagen.corpus(cfg)
+    qb = datagen.queries(cfg)
+    ix = OracleIndex(cfg.dim, cfg.vocab)
+    ix.load(c.emb, c.ids, c.term_off, c.terms)
+    state = {}
+    off = c.term_off.astype(np.int64)
+    for i in range(c.n):
+        state[int(c.ids[i])] = (c.emb[i], set(int(t) for t in c.terms[off[i]:off[i + 1]]))
+    log = datagen.update_log(cfg, c.ids, 3, 240)
+    for u in log:
+        ix.update(u.del_ids, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
+        for x in u.del_ids:
+            del state[int(x)]
+        uo = u.ins_term_off.astype(np.int64)
+        for j, x in enumerate(u.ins_ids):
+            state[int(x)] = (u.ins_emb[j], set(int(t) for t in u.ins_terms[uo[j]:uo[j + 1]]))
+        ids = list(state)
+        emb = [state[x][0] for x in ids]
+        sets = [state[x][1] for x in ids]
+        live = [True] * len(ids)
+        # a query that favours the newest rows: their mean direction
+        newest = np.asarray(u.ins_emb, dtype=np.float64).mean(axis=0)
+        extra = (newest / np.linalg.norm(newest)).astype(np.float32)
+        for q in range(qb.n + 1):
+            qe = qb.emb[q] if q < qb.n else extra
+            cnf = qb.cnf(q) if q < qb.n else []
+            want_ids, want_s, nm = brute.search(emb, ids, sets, live, qe, cnf, 25)
+            got = ix.search_one(qe, cnf, 25)
+            assert got.n_match == nm and got.ids.tolist() == want_ids, q
+            assert np.allclose(got.scores, want_s, rtol=0, atol=1e-15)
+        assert ix.n_live == len(state)
