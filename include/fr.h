@@ -122,11 +122,19 @@ typedef struct {
  * FR_EUNSUPPORTED, FR_ENOMEM, FR_EDEVICE. */
 fr_status fr_create(const fr_config* cfg, fr_index** out);
 
-/* Release everything the index owns.  NULL is allowed.  Waits for work in
- * flight on the index's streams. */
+/* Release everything the index owns (the counterpart of the pre-allocation
+ * of fr_create: the appendix, "Memory Pre-Allocation", reserves all memory
+ * when the retriever is constructed, so it is returned only here).  NULL is
+ * allowed.  Waits for work in flight on the index's streams; pointers the
+ * caller passed to earlier calls are never touched.  Always FR_OK. */
 fr_status fr_destroy(fr_index* ix);
 
-/* Replace the whole corpus by `n` documents.
+/* Replace the whole corpus by `n` documents: the dense matrices the search
+ * scans are built on the device from them (appendix, "Storing Dense
+ * Matrix": embeddings, their quantised copy and the term data are kept as
+ * separate dense device arrays; here the embeddings as 32-row matrix-core
+ * tiles and the terms as per-term document bitmaps), inside the memory
+ * reserved by fr_create (appendix, "Memory Pre-Allocation").
  * emb:      n x dim FP32, row-major (host, or device with FR_DEVICE_PTRS);
  *           values must be finite.
  * ids:      n external ids, unique, each < 0xFFFFFFFF.
@@ -139,7 +147,9 @@ fr_status fr_destroy(fr_index* ix);
 fr_status fr_load_corpus(fr_index* ix, uint64_t n, const float* emb, const uint32_t* ids,
                          const uint64_t* term_off, const uint32_t* terms, uint32_t flags);
 
-/* Delete `n_del` live ids, then insert `n_ins` new documents (same layout
+/* Keep the corpus current as jobs are created and closed (Sec. 2: the job
+ * pool changes daily, new postings appear and old ones close).
+ * Delete `n_del` live ids, then insert `n_ins` new documents (same layout
  * as fr_load_corpus, host memory), as one all-or-nothing update: the whole call is
  * validated before any device work (unknown or repeated delete id ->
  * FR_ENOTFOUND; inserting an id that stays live -> FR_EDUPID; too many
@@ -152,7 +162,14 @@ fr_status fr_update_docs(fr_index* ix, uint64_t n_del, const uint32_t* del_ids,
                          const uint64_t* ins_term_off, const uint32_t* ins_terms,
                          uint64_t* out_epoch);
 
-/* Filtered top-K for a batch of n_q queries in one pass over the corpus.
+/* Filtered top-K for a batch of n_q queries in one pass over the corpus:
+ * the hybrid retrieval of Sec. 5.3 ("System Implementation": a term
+ * predicate in conjunctive normal form, then the inner product with the
+ * query embedding, then the K best), with the appendix's "EBR" (inner
+ * product against every matching document), "Fast Top K Selection"
+ * (a score histogram bounds which documents can still reach the top K;
+ * the result is exact) and "Batch Inference" (the queries of one call
+ * share one scan of the corpus).
  * queries:   n_q x dim FP32 row-major.
  * cnf:       predicates (host, see fr_cnf_batch), cnf->n_queries == n_q.
  * k:         n_q values (host), each 0..k_max.
@@ -171,6 +188,13 @@ fr_status fr_update_docs(fr_index* ix, uint64_t n_del, const uint32_t* del_ids,
  * For BF16/FP8 indexes the approximate scores select the best min(R_q,
  * n_match) candidates by (approximate score desc, id asc), which are
  * rescored in FP32 and ordered by (FP32 score desc, id asc).
+ * Failure marker: a query whose candidates cannot be held even by the
+ * second pass (more documents tie within one score bucket than `cand_cap`)
+ * gets out_count[q] = 0xFFFFFFFF and a padding row; n_match is still
+ * exact.  A synchronous call with host buffers then returns
+ * FR_EUNSUPPORTED; an asynchronous or device-pointer call returns FR_OK
+ * when it was enqueued, so the caller must check out_count for the marker
+ * once the stream has passed the call.
  * Errors: FR_EINVAL, FR_EBUSY (FR_NOWAIT and no free workspace),
  * FR_EUNSUPPORTED, FR_EDEVICE. */
 fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_cnf_batch* cnf,

@@ -162,12 +162,29 @@ class Cnf:
         return FrCnfBatch(self.n_queries, p(self.clause_off), p(self.literal_off), p(self.terms))
 
 
+FAILED_COUNT = 0xFFFFFFFF   # out_count of a query the library could not answer
+
+
 @dataclass
 class SearchResult:
     ids: Any        # u32 [n_q, k_max]
     scores: Any     # f32 [n_q, k_max]
     count: Any      # u32 [n_q]
     n_match: Any    # u64 [n_q]
+
+    def failed(self) -> np.ndarray:
+        """Indices of the queries marked failed (count 0xFFFFFFFF).  For an
+        asynchronous search, call once its stream has passed the search."""
+        c = self.count
+        if hasattr(c, "cpu"):
+            c = c.cpu().numpy()
+        return np.flatnonzero(np.asarray(c).view(np.uint32) == FAILED_COUNT)
+
+    def raise_if_failed(self) -> None:
+        bad = self.failed()
+        if len(bad):
+            raise FrError(FR_EUNSUPPORTED, f"queries {bad[:8].tolist()} could not be answered "
+                                           "(more tied candidates than the candidate buffer holds)")
 
 
 class Index:

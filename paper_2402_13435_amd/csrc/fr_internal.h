@@ -165,6 +165,8 @@ struct SeedArgs {
   uint32_t* skey;          // [max_list][row] sample score keys (scratch)
   uint32_t row;            // skey row stride, >= n_groups * kGroup
   uint32_t* tau;
+  float* hlo;              // histogram range of the scan (narrowed here)
+  float* hinvw;
 };
 
 struct ScanArgs {
@@ -240,17 +242,6 @@ struct RescoreArgs {
   unsigned long long* out_nmatch;
 };
 
-struct MaskArgs {
-  const uint64_t* live;
-  const uint64_t* bits;
-  uint32_t vocab;
-  uint32_t n_q;
-  uint64_t n_words;        // words per query row of the output
-  const uint32_t* clause_off;
-  const uint32_t* literal_off;
-  const uint32_t* terms;
-  unsigned long long* out;
-};
 
 // Launchers (fr_kernels.hip).  Each returns the HIP error of the launch.
 hipError_t launch_tile_rows(const TileRowsArgs& a, hipStream_t s);
@@ -265,7 +256,6 @@ hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int 
                        hipStream_t s);
 hipError_t launch_select(const SelectArgs& a, hipStream_t s);
 hipError_t launch_rescore(const RescoreArgs& a, hipStream_t s);
-hipError_t launch_masks(const MaskArgs& a, uint64_t n_words_total, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 // Clear every term bit of the given slots (documents being deleted).

@@ -282,48 +282,6 @@ hipError_t launch_check_finite(const float* x, uint64_t n, uint32_t* flag, hipSt
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------- CNF masks
-// Mask word w of group g for query q: live AND over clauses of (OR over the
-// clause's literals of the term's bitmap word).  No clause -> live; an empty
-// clause -> 0.
-__device__ __forceinline__ uint64_t cnf_word(const uint64_t* __restrict__ live,
-                                             const uint64_t* __restrict__ bits, uint32_t vocab,
-                                             uint64_t g, int w, uint32_t q,
-                                             const uint32_t* __restrict__ co,
-                                             const uint32_t* __restrict__ lo,
-                                             const uint32_t* __restrict__ terms) {
-  uint64_t m = live[g * kWords + w];
-  const uint32_t c0 = co[q], c1 = co[q + 1];
-  const uint64_t* gb = bits + g * (uint64_t)vocab * kWords + w;
-  for (uint32_t c = c0; c < c1 && m; ++c) {
-    uint64_t cw = 0;
-    const uint32_t l0 = lo[c], l1 = lo[c + 1];
-    for (uint32_t l = l0; l < l1; ++l) cw |= gb[(uint64_t)terms[l] * kWords];
-    m &= cw;
-  }
-  return m;
-}
-
-__global__ __launch_bounds__(256) void k_masks(MaskArgs a, uint64_t total) {
-  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const uint32_t q = (uint32_t)(i / a.n_words);
-  const uint64_t wi = i % a.n_words;
-  a.out[i] = cnf_word(a.live, a.bits, a.vocab, wi / kWords, (int)(wi % kWords), q, a.clause_off,
-                      a.literal_off, a.terms);
-}
-hipError_t launch_masks(const MaskArgs& a, uint64_t total, hipStream_t s) {
-  if (!total) return hipSuccess;
-  FR_REQUIRE(a.live);
-  FR_REQUIRE(a.bits);
-  FR_REQUIRE(a.clause_off);
-  FR_REQUIRE(a.literal_off);
-  FR_REQUIRE(a.terms);
-  FR_REQUIRE(a.out);
-  hipLaunchKernelGGL(k_masks, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, total);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------- prep
 // One wavefront per query: the lanes clear its histogram, lane 0 sets the
 // per-query state and builds the literal table.
@@ -354,10 +312,14 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   a.nmatch[q] = 0ull;
   a.ovf[q] = 0u;
   a.qlist[q] = q;
+  // histogram range [-|q| max|x|, +|q| max|x|] (Cauchy-Schwarz), so that
+  // negative scores get buckets too; the starting-threshold kernel narrows
+  // it to [starting threshold, hi] when it finds one
   const float m = __uint_as_float(*a.norm_max);
   const float hi = a.qnorm[q] * m * 1.0001f;
-  a.hlo[q] = 0.f;
-  a.hinvw[q] = (hi > 0.f && isfinite(hi)) ? (float)kNBF / hi : 0.f;
+  const bool rng_ok = hi > 0.f && isfinite(hi);
+  a.hlo[q] = rng_ok ? -hi : 0.f;
+  a.hinvw[q] = rng_ok ? (float)kNBF / (2.f * hi) : 0.f;
   // literal table
   const uint32_t c0 = a.clause_off[q], c1 = a.clause_off[q + 1];
   const uint32_t l0 = c0 < c1 ? a.literal_off[c0] : 0u, l1 = c0 < c1 ? a.literal_off[c1] : 0u;
@@ -443,11 +405,12 @@ __global__ __launch_bounds__(256) void k_rerun(RerunArgs a) {
       if (nk > a.tau[q]) a.tau[q] = nk;
     }
   }
-  const float lo = fmaxf(key2f(a.tau[q]), 0.f);
+  const float lo = key2f(a.tau[q]);
   const float hi = key2f(a.smax[q]);
   const float span = (hi - lo) * 1.0001f;
-  a.hlo[q] = lo;
-  a.hinvw[q] = (span > 0.f && isfinite(span)) ? (float)kNBF / span : 0.f;
+  const bool ok = span > 0.f && isfinite(span) && isfinite(lo);
+  a.hlo[q] = ok ? lo : 0.f;
+  a.hinvw[q] = ok ? (float)kNBF / span : 0.f;
   a.cnt[q] = 0u;
   a.smax[q] = 0u;
   for (int i = 0; i < kHist; ++i) h[i] = 0u;
@@ -889,9 +852,18 @@ __global__ __launch_bounds__(kSelThreads) void k_seed_select(SeedArgs a) {
     const float u = 5.9604644775390625e-8f;   // 2^-24
     const float dd = (float)a.dim;
     const float gam = dd * u / (1.f - dd * u);
-    const float tol = 2.f * gam * a.qnorm[q] * __uint_as_float(*a.norm_max) * 1.125f + 1e-30f;
+    const float bound = a.qnorm[q] * __uint_as_float(*a.norm_max);
+    const float tol = 2.f * gam * bound * 1.125f + 1e-30f;
     const float tv = key2f(prefix) - tol;
     atomicMax(a.tau + q, fkey(tv));
+    // every candidate of the scan scores at least tv: the histogram range
+    // shrinks to [tv, hi], so its buckets (and the thresholds read from it)
+    // are finer
+    const float hi = bound * 1.0001f;
+    if (isfinite(tv) && tv < hi && isfinite(hi)) {
+      a.hlo[q] = tv;
+      a.hinvw[q] = (float)kNBF / (hi - tv);
+    }
   }
 }
 
@@ -911,6 +883,8 @@ hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s) {
   FR_REQUIRE(a.mw);
   FR_REQUIRE(a.skey);
   FR_REQUIRE(a.tau);
+  FR_REQUIRE(a.hlo);
+  FR_REQUIRE(a.hinvw);
   if (dt == kFP8) {
     FR_REQUIRE(a.xscale);
     FR_REQUIRE(a.qscale);

@@ -330,26 +330,9 @@ int pick_gpi(const fr_index* ix, uint32_t n_q, int qt, uint32_t n_groups) {
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 16));
 }
 
-fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int nw, int gpi,
-                         uint32_t n_groups, bool timing, const float* qsrc, uint32_t* o_ids,
-                         float* o_scores, uint32_t* o_count, unsigned long long* o_nmatch) {
-  // query rows: the workspace's padded copy (host queries), or the caller's
-  // device rows, of which the kernel then writes the padded copy that the
-  // FP32 rescoring reads
-  TileRowsArgs ta{};
-  const bool in_place = qsrc != w.qrow;
-  ta.rows = qsrc;
-  ta.n = ix->qmax;
-  ta.n_dev = w.desc;
-  ta.dim = in_place ? ix->dim : ix->dpad;
-  ta.dpad = ix->dpad;
-  ta.master = (in_place && ix->dt != kF32) ? w.qrow : nullptr;
-  ta.dt = ix->dt;
-  ta.tiles = w.qtiles;
-  ta.scale = w.qscale;
-  ta.norm = w.qnorm;
-  FR_HIP(launch_tile_rows(ta, s));
-
+// Per-query state of a search (thresholds, histograms, lists, literal
+// tables) for the batch staged in workspace w.
+PrepArgs prep_args(const fr_index* ix, Workspace& w) {
   PrepArgs pa{};
   pa.max_q = ix->qmax;
   pa.n_dev = w.desc;
@@ -377,8 +360,12 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   pa.terms = w.terms;
   pa.lit = w.lit;
   pa.linfo = w.linfo;
-  FR_HIP(launch_prep(pa, s));
+  return pa;
+}
 
+// Predicate masks of the first pass (every query of the batch) into w.mw,
+// counting each query's matches.
+MaskWordArgs mask_args(const fr_index* ix, Workspace& w, uint32_t n_groups) {
   MaskWordArgs ma{};
   ma.qlist = w.qlist;
   ma.n_list = w.desc + 1;
@@ -397,6 +384,31 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   ma.mw = w.mw;
   ma.nmatch = w.nmatch;
   ma.count_matches = 1;
+  return ma;
+}
+
+fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int nw, int gpi,
+                         uint32_t n_groups, bool timing, const float* qsrc, uint32_t* o_ids,
+                         float* o_scores, uint32_t* o_count, unsigned long long* o_nmatch) {
+  // query rows: the workspace's padded copy (host queries), or the caller's
+  // device rows, of which the kernel then writes the padded copy that the
+  // FP32 rescoring reads
+  TileRowsArgs ta{};
+  const bool in_place = qsrc != w.qrow;
+  ta.rows = qsrc;
+  ta.n = ix->qmax;
+  ta.n_dev = w.desc;
+  ta.dim = in_place ? ix->dim : ix->dpad;
+  ta.dpad = ix->dpad;
+  ta.master = (in_place && ix->dt != kF32) ? w.qrow : nullptr;
+  ta.dt = ix->dt;
+  ta.tiles = w.qtiles;
+  ta.scale = w.qscale;
+  ta.norm = w.qnorm;
+  FR_HIP(launch_tile_rows(ta, s));
+
+  FR_HIP(launch_prep(prep_args(ix, w), s));
+  const MaskWordArgs ma = mask_args(ix, w, n_groups);
   FR_HIP(launch_mask_words(ma, s));
 
   SeedArgs sd{};
@@ -417,6 +429,8 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sd.dim = ix->dim;
   sd.skey = w.skey;
   sd.tau = w.tau;
+  sd.hlo = w.hlo;
+  sd.hinvw = w.hinvw;
   FR_HIP(launch_seed(sd, ix->dt, ix->dpad, s));
 
   ScanArgs sa{};
@@ -1053,16 +1067,16 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   FR_HIP(hipEventSynchronize(w->done));
   w->in_flight = false;
   bool failed_q = false;
-  const uint32_t* cnts = dev ? nullptr : w->h_count;
-  if (!dev) {
+  const uint32_t* cnts = w->h_count;
+  if (dev) {
+    FR_HIP(hipMemcpy(w->h_count, out_count, (size_t)n_q * 4, hipMemcpyDeviceToHost));
+  } else {
     std::memcpy(out_ids, w->h_ids, kk * 4);
     std::memcpy(out_scores, w->h_scores, kk * 4);
     std::memcpy(out_count, w->h_count, n_q * 4);
     std::memcpy(out_nmatch, w->h_nmatch, n_q * 8);
   }
-  if (cnts) {
-    for (uint32_t q = 0; q < n_q; ++q) failed_q |= cnts[q] == 0xFFFFFFFFu;
-  }
+  for (uint32_t q = 0; q < n_q; ++q) failed_q |= cnts[q] == 0xFFFFFFFFu;
   if (failed_q)
     return fail(FR_EUNSUPPORTED,
                 "a query had more tied candidates than the candidate buffer holds (raise cand_cap)");
@@ -1148,33 +1162,27 @@ fr_status fr_debug_masks(fr_index* ix, const fr_cnf_batch* cnf, uint64_t* out_bi
   if (!n_q || !need) return FR_OK;
   st = wait_all(ix);
   if (st != FR_OK) return st;
+  // the search's own mask pass (prep + k_mask_words) in workspace 0, whose
+  // word-major mask buffer is then read back: these are the words the scan
+  // consumes
   Workspace& w = ix->ws[0];
+  w.h_desc[0] = n_q;
+  w.h_desc[1] = n_q;
+  w.h_desc[2] = 0;
+  w.h_desc[3] = 0;
+  std::memset(w.h_k, 0, (size_t)n_q * 4);
   st = stage_inputs(ix, w, ix->stream, n_q, cnf, n_c, n_l);
   if (st != FR_OK) return st;
-  // testing entry point: a temporary output buffer
-  unsigned long long* d_out = nullptr;
-  FR_HIP(hipMalloc(&d_out, n_q * need * 8));
-  MaskArgs ma{};
-  ma.live = ix->live;
-  ma.bits = ix->bits;
-  ma.vocab = ix->cfg.vocab;
-  ma.n_q = n_q;
-  ma.n_words = need;
-  ma.clause_off = w.clause_off;
-  ma.literal_off = w.literal_off;
-  ma.terms = w.terms;
-  ma.out = d_out;
-  hipError_t e = launch_masks(ma, n_q * need, ix->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ix->stream);
-  std::vector<uint64_t> tmp(n_q * need);
-  if (e == hipSuccess) e = hipMemcpy(tmp.data(), d_out, n_q * need * 8, hipMemcpyDeviceToHost);
-  (void)hipFree(d_out);
-  if (e != hipSuccess) {
-    ix->failed = true;
-    return fail(FR_EDEVICE, std::string("masks: ") + hipGetErrorString(e));
-  }
+  const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
+  FR_HIP(launch_prep(prep_args(ix, w), ix->stream));
+  const MaskWordArgs ma = mask_args(ix, w, n_groups);
+  FR_HIP(launch_mask_words(ma, ix->stream));
+  FR_HIP(hipStreamSynchronize(ix->stream));
+  const size_t ppad = ma.ppad;
+  std::vector<uint64_t> tmp((size_t)n_groups * kWords * ppad);
+  FR_HIP(hipMemcpy(tmp.data(), w.mw, tmp.size() * 8, hipMemcpyDeviceToHost));
   for (uint32_t q = 0; q < n_q; ++q)
-    std::memcpy(out_bits + q * n_words_per_query, tmp.data() + q * need, need * 8);
+    for (uint64_t i = 0; i < need; ++i) out_bits[q * n_words_per_query + i] = tmp[i * ppad + q];
   return FR_OK;
 }
 

@@ -26,7 +26,9 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-from .binding import Cnf, Index, SearchResult
+from .binding import FR_EUNSUPPORTED, Cnf, FrError, Index, SearchResult
+
+FAILED = 0xFFFFFFFF     # count of a query the library could not answer
 
 
 @dataclass
@@ -62,7 +64,8 @@ class Server:
         import torch
         self.torch = torch
         self.ix = index
-        self.max_batch = int(max_batch or index.max_batch)
+        # a batch never exceeds what one workspace of the index holds
+        self.max_batch = min(int(max_batch or index.max_batch), int(index.max_batch))
         self.max_wait_s = max_wait_s
         dev = torch.device("cuda", torch.cuda.current_device())
         self.dev = dev
@@ -90,8 +93,18 @@ class Server:
 
     # ------------------------------------------------------------- clients
     def submit(self, emb, cnf, k: int) -> Future:
-        r = Request(np.ascontiguousarray(emb, dtype=np.float32).reshape(-1), cnf, int(k),
-                    time.perf_counter())
+        """Queue one request; raises ValueError at once for a request the
+        index cannot take (so that it never reaches, and stalls, a batch)."""
+        emb = np.ascontiguousarray(emb, dtype=np.float32).reshape(-1)
+        if emb.shape[0] != self.ix.dim:
+            raise ValueError(f"query has {emb.shape[0]} dimensions, the index {self.ix.dim}")
+        if not 0 <= int(k) <= self.ix.k_max:
+            raise ValueError(f"K={k} outside 0..{self.ix.k_max}")
+        for clause in cnf:
+            for t in clause:
+                if not 0 <= int(t) < self.ix.vocab:
+                    raise ValueError(f"term {t} outside the vocabulary (0..{self.ix.vocab - 1})")
+        r = Request(emb, cnf, int(k), time.perf_counter())
         with self._cv:
             self._pending.append(r)
             self._cv.notify()
@@ -142,14 +155,23 @@ class Server:
             cnf = Cnf.from_lists([r.cnf for r in reqs])
             k = np.array([r.k for r in reqs], dtype=np.uint32)
             s = slot["stream"]
-            with torch.cuda.stream(s):
-                slot["q"][:n].copy_(torch.from_numpy(emb).pin_memory(), non_blocking=True)
-                out = SearchResult(slot["out"].ids[:n], slot["out"].scores[:n],
-                                   slot["out"].count[:n], slot["out"].n_match[:n])
-                with self._lock:
-                    self.ix.search(slot["q"][:n], cnf, k, out=out, stream=s)
-                ev = torch.cuda.Event()
-                ev.record(s)
+            try:
+                with torch.cuda.stream(s):
+                    slot["q"][:n].copy_(torch.from_numpy(emb).pin_memory(), non_blocking=True)
+                    out = SearchResult(slot["out"].ids[:n], slot["out"].scores[:n],
+                                       slot["out"].count[:n], slot["out"].n_match[:n])
+                    with self._lock:
+                        self.ix.search(slot["q"][:n], cnf, k, out=out, stream=s)
+                    ev = torch.cuda.Event()
+                    ev.record(s)
+            except Exception as e:   # the batch fails, the server keeps serving
+                s.synchronize()
+                with self._cv:
+                    slot["busy"] = False
+                    self._cv.notify()
+                for r in reqs:
+                    r.future.set_exception(e)
+                continue
             self.batches.append(n)
             with self._done_cv:
                 self._inflight.append((slot, reqs, ev, n))
@@ -177,6 +199,10 @@ class Server:
                 self._cv.notify()
             for i, r in enumerate(reqs):
                 c = int(cnt[i])
+                if c == FAILED:
+                    r.future.set_exception(FrError(
+                        FR_EUNSUPPORTED, "more tied candidates than the candidate buffer holds"))
+                    continue
                 r.future.set_result(Reply(ids[i, :c].copy(), sc[i, :c].copy(), int(nm[i]),
                                           r.t_arrival, t, n))
 

@@ -1,0 +1,285 @@
+"""GPU parity of the scan's less common paths, through the C ABI, against
+the FP64 oracle:
+
+* work items: several per workgroup, switching query tiles (batches larger
+  than one query tile, one group per item);
+* 8-wavefront tilings with query-block sharing (batches of 1 .. 300);
+* mixed per-query K up to 1000 (FP32 checker; BF16 with a per-query
+  rescoring depth), the autotuned tiling and the captured graph;
+* the exact selection's radix-select fallback (more than 8192 candidates at
+  or above the final threshold, from a block of tied scores);
+* thresholds over negative scores (the histogram spans [-|q| max|x|, +...]);
+* the failure marker of a query that cannot be answered, on synchronous,
+  device-pointer and asynchronous searches.
+"""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import recall_at_k, tolerance
+from helpers import check_query, gpu_index, oracle_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def big():
+    # the fp32 recipe at 300,001 documents (293 predicate groups, the last
+    # partial) and 512 queries
+    cfg = datagen.scaled(datagen.CONFIGS["fp32"], 300_001, 512)
+    c = datagen.corpus(cfg)
+    qb = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms))
+    return c, qb, oracle_for(c)
+
+
+def test_many_items_per_workgroup_and_query_tile_switch(big):
+    """Tiling (1, 4, 1): 128 queries per tile -> 4 query tiles x 293 one-group
+    items = 1172 items over the persistent workgroups (about 4.6 each), so
+    workgroups take several items and switch query tiles between them."""
+    c, qb, o = big
+    ix = gpu_index(c, k_max=100, max_batch=512)
+    ix.set_tiling(1, 4, 1)
+    res = ix.search(qb.emb, qb, 100)
+    print(f"[paths] (1,4,1): {ix.stats().n_passes} pass(es)", flush=True)
+    for q in range(qb.n):
+        check_query(o, qb, q, res, 100)
+    # other tilings (query tiles of 256 and 128 queries, several groups per
+    # item, the default) give the same rows bit for bit
+    for til in ((1, 8, 1), (2, 4, 3), (1, 8, 4), (0, 0, 0)):
+        ix.set_tiling(*til)
+        t = ix.search(qb.emb, qb, 100)
+        assert np.array_equal(t.ids, res.ids), til
+        assert np.array_equal(t.scores, res.scores), til
+        assert np.array_equal(t.n_match, res.n_match), til
+    ix.close()
+
+
+def test_eight_wave_query_block_sharing(big):
+    """With 8 compute wavefronts a batch of 1, 32 or 64 queries fills 1 or 2
+    of the 8 query blocks, which the idle wavefronts share (tile stride 8 or
+    4); 300 queries leave the second query tile partial.  Every sub-batch's
+    rows equal the full batch's."""
+    c, qb, o = big
+    ix = gpu_index(c, k_max=100, max_batch=512)
+    ix.set_tiling(1, 8, 4)
+    full = ix.search(qb.emb, qb, 100)
+    for q in range(0, qb.n, 37):
+        check_query(o, qb, q, full, 100)
+    for n, g in ((1, 4), (32, 4), (64, 1), (300, 4), (300, 1)):
+        idx = list(range(7, 7 + n))
+        sub = qb.subset(idx)
+        ix.set_tiling(1, 8, g)
+        r = ix.search(sub.emb, sub, 100)
+        assert np.array_equal(r.ids, full.ids[idx]), (n, g)
+        assert np.array_equal(r.scores, full.scores[idx]), (n, g)
+        assert np.array_equal(r.n_match, full.n_match[idx]), (n, g)
+    ix.close()
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    # the batching recipe (V=16384, selectivity 1e-5..0.5, K in {10,100,1000})
+    # at 200,000 documents and 192 queries
+    cfg = datagen.scaled(datagen.CONFIGS["batching"], 200_000, 192)
+    c = datagen.corpus(cfg)
+    qb = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms))
+    assert set(np.unique(qb.k).tolist()) == {10, 100, 1000}
+    return c, qb, oracle_for(c)
+
+
+def test_mixed_k_f32_autotuned(mixed):
+    c, qb, o = mixed
+    ix = gpu_index(c, k_max=1000, max_batch=256)
+    default = ix.search(qb.emb, qb, qb.k)
+    for q in range(qb.n):
+        check_query(o, qb, q, default, int(qb.k[q]))
+    til = ix.autotune(qb.emb, qb, qb.k)
+    print(f"[paths] autotuned tiling {til}", flush=True)
+    tuned = ix.search(qb.emb, qb, qb.k)
+    assert np.array_equal(tuned.ids, default.ids) and np.array_equal(tuned.scores, default.scores)
+    assert np.array_equal(tuned.count, default.count)
+    ix.close()
+
+
+def test_mixed_k_bf16_rescore_min_graph(mixed):
+    """BF16 first pass with R_q = min(4096, max(1024, 4 K_q)) rescored in
+    FP32; the autotuned tiling; eager and graph replays agree bit for bit."""
+    torch = pytest.importorskip("torch")
+    c, qb, o = mixed
+    tol = tolerance(c.cfg.dim)
+    ix = gpu_index(c, k_max=1000, dtype="bf16", rescore_r=4096, rescore_min=1024,
+                   max_batch=256, n_workspaces=2)
+    ix.autotune(qb.emb, qb, qb.k)
+    res = ix.search(qb.emb, qb, qb.k)
+    got, want = [], []
+    for q in range(qb.n):
+        k = int(qb.k[q])
+        a = o.search_one(qb.emb[q], qb.cnf(q), k)
+        cnt = int(res.count[q])
+        assert cnt == a.count and int(res.n_match[q]) == a.n_match, q
+        ids = res.ids[q, :cnt]
+        if cnt:
+            s = res.scores[q, :cnt].astype(np.float64)
+            assert np.abs(s - o.score_ids(qb.emb[q], ids)).max() <= tol, q
+            assert np.all(np.diff(s) <= 0)
+        got.append(ids.tolist())
+        want.append(a.ids.tolist())
+    rec, _ = recall_at_k(got, want)
+    assert rec >= 0.99, rec
+    # the captured graph, replayed, gives the eager rows
+    dev = torch.device("cuda:0")
+    qd = torch.from_numpy(qb.emb).to(dev)
+    s = torch.cuda.Stream()
+    for _ in range(3):
+        g = ix.search(qd, qb, qb.k, stream=s, graph=True)
+        s.synchronize()
+        assert len(g.failed()) == 0
+        assert np.array_equal(g.ids.cpu().numpy().view(np.uint32), res.ids)
+        assert np.array_equal(g.scores.cpu().numpy(), res.scores)
+        e = ix.search(qb.emb, qb, qb.k)
+        assert np.array_equal(e.ids, res.ids)
+    ix.close()
+
+
+def _tied_corpus(d=64, n_tied=20_000, n_high=3_000, n_rest=17_000, seed=3):
+    """Documents scoring exactly 1.0 against e_0 (n_tied copies of e_0),
+    some scoring in (0.6, 0.9) and the rest below 0.5; one term each."""
+    rng = np.random.default_rng(seed)
+    n = n_tied + n_high + n_rest
+    emb = np.zeros((n, d), np.float32)
+    emb[:n_tied, 0] = 1.0
+    x = rng.standard_normal((n_high + n_rest, d))
+    x[:, 0] = 0.0
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    h = np.concatenate([rng.uniform(0.6, 0.9, n_high), rng.uniform(-0.5, 0.5, n_rest)])
+    x = x * np.sqrt(1.0 - h ** 2)[:, None]
+    x[:, 0] = h
+    emb[n_tied:] = x.astype(np.float32)
+    perm = rng.permutation(n)
+    emb = emb[perm]
+    ids = (rng.permutation(4 * n)[:n] + 1).astype(np.uint32)
+    cfg = datagen.scaled(datagen.CONFIGS["tiny"], n, 2)
+    return SimpleNamespace(emb=emb, ids=ids, term_off=np.arange(n + 1, dtype=np.int64),
+                           terms=np.zeros(n, np.uint32), n=n, cfg=cfg)
+
+
+def test_select_radix_fallback_on_ties():
+    """20,000 documents tie at score 1.0: with K = 4096 every one of them is
+    at or above the final threshold, more than the 8192 the selection sorts
+    in LDS, so it takes the radix-select path; the answer is the 4096
+    smallest ids among the ties.  A second query (-e_0, no clause) ranks
+    the same corpus the other way round in the same batch."""
+    c = _tied_corpus()
+    o = oracle_for(c)
+    ix = gpu_index(c, k_max=4096)
+    q = np.zeros((2, c.cfg.dim), np.float32)
+    q[0, 0] = 1.0
+    q[1, 0] = -1.0
+    batch = datagen.from_cnf_lists(q, [[[0]], []], [4096, 4096])
+    res = ix.search(q, batch, 4096)
+    st = ix.stats()
+    print(f"[paths] ties: {st.candidates} candidates, {st.n_passes} pass(es)", flush=True)
+    tied = np.sort(c.ids[c.emb[:, 0] == 1.0])
+    assert np.array_equal(res.ids[0], tied[:4096])
+    assert np.all(res.scores[0] == 1.0)
+    for i in range(2):
+        check_query(o, batch, i, res, 4096)
+    ix.close()
+
+
+def test_negative_scores_raise_the_threshold():
+    """Every match of the query scores below zero, the matches sit outside
+    the starting threshold's sample (groups 33-40 of a 40-group corpus), and
+    they outnumber the candidate buffer: the threshold must still rise from
+    the histogram, so the search answers exactly instead of failing."""
+    rng = np.random.default_rng(11)
+    d, n_groups = 64, 40
+    n = n_groups * 1024
+    x = rng.standard_normal((n, d))
+    x[:, 0] = 0.0
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    s = rng.uniform(-0.99, -0.4, n)
+    x = x * np.sqrt(1.0 - s ** 2)[:, None]
+    x[:, 0] = s
+    emb = x.astype(np.float32)
+    lists = [[0, 1] if i >= 33 * 1024 and i % 2 == 0 else [0] for i in range(n)]
+    off = np.cumsum([0] + [len(t) for t in lists]).astype(np.int64)
+    terms = np.concatenate([np.asarray(t, np.uint32) for t in lists])
+    cfg = datagen.scaled(datagen.CONFIGS["tiny"], n, 2)
+    c = SimpleNamespace(emb=emb, ids=np.arange(n, dtype=np.uint32) * 7 + 3, term_off=off,
+                        terms=terms, n=n, cfg=cfg)
+    o = oracle_for(c)
+    ix = gpu_index(c, k_max=16, cand_cap=1024)
+    q = np.zeros((2, d), np.float32)
+    q[:, 0] = 1.0
+    batch = datagen.from_cnf_lists(q, [[[1]], [[1], [0]]], [16, 16])
+    res = ix.search(q, batch, 16)
+    assert int(res.n_match[0]) == int(np.sum([1 in t for t in lists]))
+    for i in range(2):
+        check_query(o, batch, i, res, 16)
+        assert np.all(res.scores[i, :16] < 0)
+    ix.close()
+
+
+def _all_tied_index(torch_dev=False):
+    from paper_2402_13435_amd import Index
+    rng = np.random.default_rng(2)
+    row = rng.standard_normal((1, 64)).astype(np.float32)
+    emb = np.repeat(row, 200, axis=0)
+    ix = Index(1000, 64, 4, 16, cand_cap=64)
+    ix.load_corpus(emb, np.arange(200, dtype=np.uint32), np.arange(201), np.zeros(200, np.uint32))
+    return ix, row
+
+
+def test_failure_marker_on_device_and_async_searches():
+    """200 identical rows tie above any threshold and do not fit a 64-entry
+    candidate buffer: the query is marked failed (count 0xFFFFFFFF).  A
+    synchronous search with device tensors raises like the host one; an
+    asynchronous one returns, and the marker is in its counts."""
+    torch = pytest.importorskip("torch")
+    from paper_2402_13435_amd import FrError
+    from paper_2402_13435_amd.binding import FR_EUNSUPPORTED
+    ix, row = _all_tied_index()
+    batch = datagen.from_cnf_lists(row, [[]], [16])
+    with pytest.raises(FrError) as e:
+        ix.search(row, batch, 16)
+    assert e.value.status == FR_EUNSUPPORTED
+    qd = torch.from_numpy(row).cuda()
+    with pytest.raises(FrError) as e:
+        ix.search(qd, batch, 16)
+    assert e.value.status == FR_EUNSUPPORTED
+    s = torch.cuda.Stream()
+    out = ix.search(qd, batch, 16, stream=s)
+    s.synchronize()
+    assert out.failed().tolist() == [0]
+    with pytest.raises(FrError):
+        out.raise_if_failed()
+    assert int(out.n_match.cpu()[0]) == 200
+    # a query that can be answered on the same index is unaffected
+    ok = ix.search(row, datagen.from_cnf_lists(row, [[[3]]], [16]), 16)
+    assert ok.count[0] == 0
+    ix.close()
+
+
+def test_server_rejects_bad_requests_and_reports_failed_queries():
+    from paper_2402_13435_amd import FrError
+    from paper_2402_13435_amd.serve import Server
+    ix, row = _all_tied_index()
+    srv = Server(ix, slots=1, max_batch=4096)          # clamped to the index's max_batch
+    assert srv.max_batch == ix.max_batch
+    with pytest.raises(ValueError):
+        srv.submit(row[0], [], 17)                       # K > k_max
+    with pytest.raises(ValueError):
+        srv.submit(row[0], [[4]], 10)                    # term outside the vocabulary
+    with pytest.raises(ValueError):
+        srv.submit(row[0, :10], [], 10)                  # wrong dimension
+    bad = srv.submit(row[0], [], 16)                     # cannot be answered
+    with pytest.raises(FrError):
+        bad.result(timeout=60)
+    good = srv.submit(row[0], [[3]], 16)                 # the server keeps serving
+    rep = good.result(timeout=60)
+    assert rep.n_match == 0 and len(rep.ids) == 0
+    srv.close()
+    ix.close()

@@ -2,6 +2,7 @@
 batches equal the same requests searched alone."""
 import threading
 import time
+from types import SimpleNamespace
 
 import numpy as np
 import pytest
@@ -64,9 +65,16 @@ def test_updates_between_batches_are_visible():
         srv.update(u.del_ids, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
         o.update(u.del_ids, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
         futs = [srv.submit(qb.emb[q], qb.cnf(q), 10) for q in range(qb.n)]
-        for q, f in enumerate(futs):
-            rep = f.result(timeout=60)
-            a = o.search_one(qb.emb[q], qb.cnf(q), 10)
-            assert rep.n_match == a.n_match
-            assert set(rep.ids.tolist()) <= set(int(x) for x in o.ids[o.live])
+        reps = [f.result(timeout=60) for f in futs]
+        # the served rows, padded like a search result, through the checker
+        ids = np.full((qb.n, 10), 0xFFFFFFFF, np.uint32)
+        sc = np.full((qb.n, 10), -np.inf, np.float32)
+        for q, rep in enumerate(reps):
+            ids[q, :len(rep.ids)] = rep.ids
+            sc[q, :len(rep.ids)] = rep.scores
+        res = SimpleNamespace(ids=ids, scores=sc,
+                              count=np.array([len(r.ids) for r in reps], np.uint32),
+                              n_match=np.array([r.n_match for r in reps], np.uint64))
+        for q in range(qb.n):
+            check_query(o, qb, q, res, 10)
     srv.close()
