@@ -201,6 +201,30 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
                     const uint32_t* k, uint32_t* out_ids, float* out_scores,
                     uint32_t* out_count, uint64_t* out_nmatch, void* stream, uint32_t flags);
 
+/* fr_search for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same search as fr_search with FR_DEVICE_PTRS (same arguments, results and
+ * failure marker; `flags` must hold FR_DEVICE_PTRS and may add FR_ASYNC),
+ * but the per-search device memory (query tiles, thresholds, histograms,
+ * candidate buffers, predicate masks, selection buffers) is laid out in a
+ * fixed 128 MiB scratch array that each device holds in the library's code
+ * object until the process ends; the call makes no allocation of any kind.
+ * The caller passes device queries and device outputs as for fr_search.
+ * Limit: the call's workspace (about n_q x (cand_cap x 8 + 128 KiB FP32 or
+ * 256 KiB BF16/FP8 + rescore_r x 12) bytes plus 32 KiB per 1024 documents
+ * for every started block of 256 queries) must fit in the 128 MiB; a larger
+ * request fails with FR_EINVAL and a message, before any device work.  For
+ * example 256 FP32 queries over 1M documents with the default cand_cap fit.
+ * Every call on one device shares that device's scratch, which keeps the
+ * last call's contents (each call initialises what it reads): calls that
+ * overlap in time on one device, from any index or stream, race and must be
+ * ordered by the caller (the same stream, or events).
+ * Errors: FR_EINVAL, FR_EUNSUPPORTED, FR_EDEVICE. */
+fr_status fr_search_noalloc(fr_index* ix, uint32_t n_q, const float* queries,
+                            const fr_cnf_batch* cnf, const uint32_t* k, uint32_t* out_ids,
+                            float* out_scores, uint32_t* out_count, uint64_t* out_nmatch,
+                            void* stream, uint32_t flags);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* fr_last_error(void);
 

@@ -71,6 +71,8 @@ SYMBOLS = {
                                       _vp, _vp, _u64p]),
     "fr_search": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.POINTER(FrCnfBatch), _vp,
                                  _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32]),
+    "fr_search_noalloc": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.POINTER(FrCnfBatch),
+                                         _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32]),
     "fr_last_error": (ctypes.c_char_p, []),
     "fr_stats": (ctypes.c_int, [_vp, ctypes.POINTER(FrStats)]),
     "fr_info": (ctypes.c_int, [_vp, _u64p, _u64p, _u64p]),
@@ -288,6 +290,21 @@ class Index:
         _check(lib().fr_search(self._h, n_q, _ptr(queries), ctypes.byref(st), _ptr(k),
                                _ptr(out.ids), _ptr(out.scores), _ptr(out.count),
                                _ptr(out.n_match), s, flags))
+        return out
+
+    def search_noalloc(self, queries, cnf, k, out: SearchResult, stream=None) -> SearchResult:
+        """fr_search_noalloc: device ``queries`` and device outputs ``out``
+        (the caller allocates them); the search itself allocates nothing.
+        Asynchronous on ``stream`` when one is given."""
+        cnf = Cnf.of(cnf)
+        n_q = cnf.n_queries
+        k = _host(np.broadcast_to(np.asarray(k, dtype=np.uint32), (n_q,)), np.uint32)
+        flags = FR_DEVICE_PTRS | (FR_ASYNC if stream is not None else 0)
+        st = cnf.struct()
+        _check(lib().fr_search_noalloc(self._h, n_q, _ptr(queries), ctypes.byref(st), _ptr(k),
+                                       _ptr(out.ids), _ptr(out.scores), _ptr(out.count),
+                                       _ptr(out.n_match), getattr(stream, "cuda_stream", stream),
+                                       flags))
         return out
 
     def stats(self) -> FrStats:

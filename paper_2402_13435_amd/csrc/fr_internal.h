@@ -21,6 +21,10 @@ constexpr int kMaxR = 4096;          // largest K / R handled by select and resc
 constexpr int kSeedGroupsF32 = 32;
 constexpr int kSeedGroupsLow = 64;
 constexpr int kLits = 12;            // literals per query in the scan's fast mask path
+// device scratch of fr_search_noalloc (one array per device, in the code
+// object) and the device ordinals it is looked up for
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 64;
 constexpr uint32_t kKeyNegInf = 0x007FFFFFu;  // order key of -inf
 constexpr uint32_t kKeyPosInf = 0xFF800000u;  // order key of +inf
 
@@ -263,6 +267,9 @@ hipError_t launch_clear_slot_terms(const uint32_t* slots, uint64_t n, uint64_t* 
                                    uint32_t vocab, hipStream_t s);
 // flag |= 1 if any of x[0..n) is not finite.
 hipError_t launch_check_finite(const float* x, uint64_t n, uint32_t* flag, hipStream_t s);
+// Device address of the no-allocation scratch (kScratchBytes) on `device`,
+// which must be the current device; looked up once per device.
+hipError_t scratch_address(int device, void** out);
 // Scan variants: query blocks of 32 per wavefront x wavefronts per workgroup.
 bool scan_supported(int dt, int dpad, int qb, int nw);
 

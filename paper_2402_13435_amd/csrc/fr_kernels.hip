@@ -29,6 +29,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "fr_internal.h"
 
 namespace fr {
@@ -110,6 +112,34 @@ static inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 65535
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return (unsigned)g;
+}
+
+// --------------------------------------------------- no-allocation scratch
+// Device memory of the searches made through fr_search_noalloc: a fixed
+// array in the code object, so that such a search needs no allocation.  Each
+// device that loads the library holds its own copy until the process ends.
+// On the host its name is only a stand-in: kernels get the device address
+// that hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;   // the caller makes `device` current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {

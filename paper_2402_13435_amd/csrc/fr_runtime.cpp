@@ -66,6 +66,10 @@ uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 }  // namespace
 
 struct Workspace {
+  // sizes the buffers below were laid out for: queries, clauses and
+  // literals per search, row stride of the masks, candidate slots per
+  // query, row stride of the starting-threshold sample
+  uint32_t qcap = 0, cmax = 0, lmax = 0, ppad = 0, cand_cap = 0, seed_row = 0;
   // device
   float* qrow = nullptr;
   uint8_t* qtiles = nullptr;
@@ -177,11 +181,95 @@ struct fr_index {
   bool have_last = false;
   size_t last_ws = 0;
   std::vector<std::pair<uint32_t, uint32_t>> history;  // (workspace, ring slot) per call
+  // fr_search_noalloc: the device's scratch array, a pinned input block
+  // (sized like a workspace's) with the event of its last copy, and a pinned
+  // count buffer for the synchronous failure check
+  uint8_t* scratch = nullptr;
+  uint32_t* na_h_in = nullptr;
+  uint32_t* na_h_count = nullptr;
+  hipEvent_t na_copied = nullptr;
+  bool na_pending = false;
   std::mutex mu;
 };
 
-// row stride (positions) of a workspace's predicate-mask buffer
-static uint32_t mask_ppad(const fr_index* ix) { return round_up(ix->qmax, 256); }
+namespace {
+
+template <class T>
+void carve(T** p, uint8_t* base, size_t& off, size_t count) {
+  *p = base ? (T*)(base + off) : nullptr;
+  off += (std::max<size_t>(count * sizeof(T), 1) + 255) / 256 * 256;
+}
+
+// Device buffers of a search workspace for qm queries, cm clauses and lm
+// literals per search over n_groups corpus groups, laid out in one block at
+// `base` (256-byte aligned pieces); `outputs` adds the result buffers that
+// host-pointer searches copy back from.  Sets the workspace's sizes and
+// returns the block's size; with base == nullptr it only computes it.
+size_t layout_workspace(const fr_index* ix, Workspace& w, uint8_t* base, uint32_t qm,
+                        uint32_t cm, uint32_t lm, uint64_t n_groups, uint32_t cand_cap,
+                        bool outputs) {
+  w.qcap = qm;
+  w.cmax = cm;
+  w.lmax = lm;
+  w.ppad = round_up(std::max<uint32_t>(qm, 1), 256);
+  w.cand_cap = cand_cap;
+  w.seed_row = ix->seed_groups * kGroup;
+  const size_t tb = tile_bytes(ix->dt, ix->dpad);
+  size_t off = 0;
+  carve(&w.qrow, base, off, (size_t)qm * ix->dpad);
+  carve(&w.qtiles, base, off, (size_t)round_up(qm, kTile) / kTile * tb);
+  carve(&w.qscale, base, off, qm);
+  carve(&w.qnorm, base, off, qm);
+  // per-search inputs: [desc 4][k qm][clause_off qm+1][literal_off cm+1][terms lm]
+  carve(&w.in, base, off, 4 + (size_t)qm + (qm + 1) + (cm + 1) + lm);
+  if (w.in) {
+    w.desc = w.in;
+    w.k = w.desc + 4;
+    w.clause_off = w.k + qm;
+    w.literal_off = w.clause_off + qm + 1;
+    w.terms = w.literal_off + cm + 1;
+  }
+  carve(&w.kp, base, off, qm);
+  carve(&w.tau, base, off, qm);
+  carve(&w.cnt, base, off, qm);
+  carve(&w.smax, base, off, qm);
+  carve(&w.hist, base, off, (size_t)qm * kHist);
+  carve(&w.qlist, base, off, qm);
+  carve(&w.qlist2, base, off, qm);
+  carve(&w.ovf, base, off, qm);
+  carve(&w.sel_cnt, base, off, qm);
+  carve(&w.lit, base, off, (size_t)qm * kLits);
+  carve(&w.linfo, base, off, qm);
+  carve(&w.work, base, off, kXcds);
+  carve(&w.hlo, base, off, qm);
+  carve(&w.hinvw, base, off, qm);
+  carve(&w.nmatch, base, off, qm);
+  carve(&w.cand_key, base, off, (size_t)qm * cand_cap);
+  carve(&w.skey, base, off, (size_t)qm * w.seed_row);
+  // the scan's padding loads read the first 4096 words of the masks
+  carve(&w.mw, base, off, std::max<size_t>((size_t)n_groups * kWords * w.ppad, 4096));
+  carve(&w.sel_key, base, off, (size_t)qm * ix->rmax);
+  carve(&w.sel_slot, base, off, (size_t)qm * ix->rmax);
+  if (outputs) {
+    carve(&w.out_ids, base, off, (size_t)qm * ix->cfg.k_max);
+    carve(&w.out_scores, base, off, (size_t)qm * ix->cfg.k_max);
+    carve(&w.out_count, base, off, qm);
+    carve(&w.out_nmatch, base, off, qm);
+  }
+  return off;
+}
+
+// The pinned twin of a workspace's input block, same layout.
+void layout_host_inputs(Workspace& w, uint32_t* h_in) {
+  w.h_in = h_in;
+  w.h_desc = h_in;
+  w.h_k = w.h_desc + 4;
+  w.h_co = w.h_k + w.qcap;
+  w.h_lo = w.h_co + w.qcap + 1;
+  w.h_terms = w.h_lo + w.cmax + 1;
+}
+
+}  // namespace
 
 namespace {
 
@@ -334,7 +422,7 @@ int pick_gpi(const fr_index* ix, uint32_t n_q, int qt, uint32_t n_groups) {
 // tables) for the batch staged in workspace w.
 PrepArgs prep_args(const fr_index* ix, Workspace& w) {
   PrepArgs pa{};
-  pa.max_q = ix->qmax;
+  pa.max_q = w.qcap;
   pa.n_dev = w.desc;
   pa.k = w.k;
   pa.kp = w.kp;
@@ -369,10 +457,10 @@ MaskWordArgs mask_args(const fr_index* ix, Workspace& w, uint32_t n_groups) {
   MaskWordArgs ma{};
   ma.qlist = w.qlist;
   ma.n_list = w.desc + 1;
-  ma.max_list = ix->qmax;
-  ma.ppad = mask_ppad(ix);
+  ma.max_list = w.qcap;
+  ma.ppad = w.ppad;
   ma.n_groups = n_groups;
-  ma.gpt = std::max<uint32_t>(1, std::min<uint32_t>(16, (uint32_t)(((uint64_t)n_groups * ix->qmax) >> 18)));
+  ma.gpt = std::max<uint32_t>(1, std::min<uint32_t>(16, (uint32_t)(((uint64_t)n_groups * w.qcap) >> 18)));
   ma.live = ix->live;
   ma.bits = ix->bits;
   ma.vocab = ix->cfg.vocab;
@@ -396,7 +484,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   TileRowsArgs ta{};
   const bool in_place = qsrc != w.qrow;
   ta.rows = qsrc;
-  ta.n = ix->qmax;
+  ta.n = w.qcap;
   ta.n_dev = w.desc;
   ta.dim = in_place ? ix->dim : ix->dpad;
   ta.dpad = ix->dpad;
@@ -414,7 +502,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   SeedArgs sd{};
   sd.qlist = w.qlist;
   sd.n_list = w.desc + 1;
-  sd.max_list = ix->qmax;
+  sd.max_list = w.qcap;
   sd.kp = w.kp;
   sd.tiles = ix->tiles;
   sd.xscale = ix->xscale;
@@ -425,7 +513,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sd.mw = w.mw;
   sd.ppad = ma.ppad;
   sd.n_groups = std::min(n_groups, ix->seed_groups);
-  sd.row = ix->seed_groups * kGroup;
+  sd.row = w.seed_row;
   sd.dim = ix->dim;
   sd.skey = w.skey;
   sd.tau = w.tau;
@@ -452,7 +540,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sa.hlo = w.hlo;
   sa.hinvw = w.hinvw;
   sa.cand_key = w.cand_key;
-  sa.cap = ix->cand_cap;
+  sa.cap = w.cand_cap;
   sa.work = w.work;
   sa.gpi = (uint32_t)gpi;
   sa.mw = w.mw;
@@ -464,14 +552,14 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   SelectArgs se{};
   se.qlist = w.qlist;
   se.n_list = w.desc + 1;
-  se.max_list = ix->qmax;
+  se.max_list = w.qcap;
   se.final_pass = 0;
   se.kp = w.kp;
   se.tau = w.tau;
   se.cnt = w.cnt;
   se.cand_key = w.cand_key;
   se.slot_ids = ix->slot_ids;
-  se.cap = ix->cand_cap;
+  se.cap = w.cand_cap;
   se.sel_key = w.sel_key;
   se.sel_slot = w.sel_slot;
   se.sel_cnt = w.sel_cnt;
@@ -489,7 +577,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
 
   // second pass for overflowed queries (an empty list when none did)
   RerunArgs ra{};
-  ra.max_q = ix->qmax;
+  ra.max_q = w.qcap;
   ra.n_dev = w.desc;
   ra.ovf = w.ovf;
   ra.qlist2 = w.qlist2;
@@ -520,7 +608,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
 
   if (ix->dt != kF32) {
     RescoreArgs rs{};
-    rs.max_q = ix->qmax;
+    rs.max_q = w.qcap;
     rs.n_dev = w.desc;
     rs.ovf = w.ovf;
     rs.master = ix->master;
@@ -718,48 +806,16 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   const uint32_t nws = cfg->n_workspaces ? cfg->n_workspaces : 1;
   ix->ws.resize(nws);
   const uint32_t qm = ix->qmax, qpad = round_up(qm, kTile);
+  const size_t n_in = 4 + (size_t)qm + (qm + 1) + (ix->cmax + 1) + ix->lmax;
   for (auto& w : ix->ws) {
-    FR_ALLOC(dalloc(&w.qrow, (size_t)qm * ix->dpad, D));
-    FR_ALLOC(dalloc(&w.qtiles, (size_t)qpad / kTile * tb, D));
-    FR_ALLOC(dalloc(&w.qscale, qm, D));
-    FR_ALLOC(dalloc(&w.qnorm, qm, D));
-    const size_t n_in = 4 + (size_t)qm + (qm + 1) + (ix->cmax + 1) + ix->lmax;
-    FR_ALLOC(dalloc(&w.in, n_in, D));
-    FR_ALLOC(halloc(&w.h_in, n_in, H));
-    w.desc = w.in;
-    w.k = w.desc + 4;
-    w.clause_off = w.k + qm;
-    w.literal_off = w.clause_off + qm + 1;
-    w.terms = w.literal_off + ix->cmax + 1;
-    w.h_desc = w.h_in;
-    w.h_k = w.h_desc + 4;
-    w.h_co = w.h_k + qm;
-    w.h_lo = w.h_co + qm + 1;
-    w.h_terms = w.h_lo + ix->cmax + 1;
-    FR_ALLOC(dalloc(&w.kp, qm, D));
-    FR_ALLOC(dalloc(&w.tau, qm, D));
-    FR_ALLOC(dalloc(&w.cnt, qm, D));
-    FR_ALLOC(dalloc(&w.smax, qm, D));
-    FR_ALLOC(dalloc(&w.hist, (size_t)qm * kHist, D));
-    FR_ALLOC(dalloc(&w.qlist, qm, D));
-    FR_ALLOC(dalloc(&w.qlist2, qm, D));
-    FR_ALLOC(dalloc(&w.ovf, qm, D));
-    FR_ALLOC(dalloc(&w.sel_cnt, qm, D));
-    FR_ALLOC(dalloc(&w.lit, (size_t)qm * kLits, D));
-    FR_ALLOC(dalloc(&w.linfo, qm, D));
-    FR_ALLOC(dalloc(&w.work, kXcds, D));
-    FR_ALLOC(dalloc(&w.hlo, qm, D));
-    FR_ALLOC(dalloc(&w.hinvw, qm, D));
-    FR_ALLOC(dalloc(&w.nmatch, qm, D));
-    FR_ALLOC(dalloc(&w.cand_key, (size_t)qm * ix->cand_cap, D));
-    FR_ALLOC(dalloc(&w.skey, (size_t)qm * ix->seed_groups * kGroup, D));
-    FR_ALLOC(dalloc(&w.mw, (size_t)(ix->cap / kGroup) * kWords * mask_ppad(ix), D));
-    FR_ALLOC(dalloc(&w.sel_key, (size_t)qm * ix->rmax, D));
-    FR_ALLOC(dalloc(&w.sel_slot, (size_t)qm * ix->rmax, D));
-    FR_ALLOC(dalloc(&w.out_ids, (size_t)qm * cfg->k_max, D));
-    FR_ALLOC(dalloc(&w.out_scores, (size_t)qm * cfg->k_max, D));
-    FR_ALLOC(dalloc(&w.out_count, qm, D));
-    FR_ALLOC(dalloc(&w.out_nmatch, qm, D));
+    const size_t bytes = layout_workspace(ix, w, nullptr, qm, ix->cmax, ix->lmax,
+                                          cap / kGroup, ix->cand_cap, true);
+    uint8_t* block = nullptr;
+    FR_ALLOC(dalloc(&block, bytes, D));
+    layout_workspace(ix, w, block, qm, ix->cmax, ix->lmax, cap / kGroup, ix->cand_cap, true);
+    uint32_t* h_in = nullptr;
+    FR_ALLOC(halloc(&h_in, n_in, H));
+    layout_host_inputs(w, h_in);
     FR_ALLOC(halloc(&w.h_q, (size_t)qm * ix->dpad, H));
     FR_ALLOC(halloc(&w.h_ids, (size_t)qm * cfg->k_max, H));
     FR_ALLOC(halloc(&w.h_scores, (size_t)qm * cfg->k_max, H));
@@ -777,6 +833,22 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
       return fail(FR_EDEVICE, "hipEventCreate failed");
     }
     std::memset(w.h_q, 0, (size_t)qm * ix->dpad * sizeof(float));
+  }
+  // fr_search_noalloc: the device's scratch (looked up once per device,
+  // with the device current), its pinned input block and events
+  {
+    void* sp = nullptr;
+    if (scratch_address(cfg->device, &sp) != hipSuccess) {
+      cleanup();
+      return fail(FR_EDEVICE, "hipGetSymbolAddress of the search scratch failed");
+    }
+    ix->scratch = (uint8_t*)sp;
+  }
+  FR_ALLOC(halloc(&ix->na_h_in, n_in, H));
+  FR_ALLOC(halloc(&ix->na_h_count, qm, H));
+  if (hipEventCreateWithFlags(&ix->na_copied, hipEventDisableTiming) != hipSuccess) {
+    cleanup();
+    return fail(FR_EDEVICE, "hipEventCreate failed");
   }
 #undef FR_ALLOC
   // initial state: empty corpus, zero padding everywhere
@@ -813,6 +885,10 @@ fr_status fr_destroy(fr_index* ix) {
         if (w.r1[i]) (void)hipEventDestroy(w.r1[i]);
         if (w.r2[i]) (void)hipEventDestroy(w.r2[i]);
       }
+    }
+    if (ix->na_copied) {
+      (void)hipEventSynchronize(ix->na_copied);
+      (void)hipEventDestroy(ix->na_copied);
     }
     if (ix->stream) {
       (void)hipStreamSynchronize(ix->stream);
@@ -1080,6 +1156,70 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   if (failed_q)
     return fail(FR_EUNSUPPORTED,
                 "a query had more tied candidates than the candidate buffer holds (raise cand_cap)");
+  return FR_OK;
+}
+
+fr_status fr_search_noalloc(fr_index* ix, uint32_t n_q, const float* queries,
+                            const fr_cnf_batch* cnf, const uint32_t* k, uint32_t* out_ids,
+                            float* out_scores, uint32_t* out_count, uint64_t* out_nmatch,
+                            void* stream, uint32_t flags) {
+  if (!ix) return fail(FR_EINVAL, "null index");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (ix->failed) return fail(FR_EDEVICE, "index failed earlier");
+  if (!(flags & FR_DEVICE_PTRS))
+    return fail(FR_EINVAL, "fr_search_noalloc takes device queries and outputs (FR_DEVICE_PTRS)");
+  if (flags & (FR_GRAPH | FR_NOWAIT))
+    return fail(FR_EINVAL, "FR_GRAPH and FR_NOWAIT do not apply to fr_search_noalloc");
+  FR_HIP(hipSetDevice(ix->cfg.device));
+  const bool async = stream || (flags & FR_ASYNC);
+  if (n_q > ix->qmax) return fail(FR_EINVAL, "n_q exceeds max_batch");
+  uint32_t n_c = 0, n_l = 0;
+  fr_status st = validate_cnf(ix, n_q, cnf, &n_c, &n_l);
+  if (st != FR_OK) return st;
+  if (n_q == 0) return FR_OK;
+  if (!queries || !k || !out_ids || !out_scores || !out_count || !out_nmatch)
+    return fail(FR_EINVAL, "null query or output pointer");
+  for (uint32_t q = 0; q < n_q; ++q)
+    if (k[q] > ix->cfg.k_max) return fail(FR_EINVAL, "k exceeds k_max");
+  // this call's workspace, laid out in the device's scratch array
+  const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
+  Workspace w;
+  const size_t need = layout_workspace(ix, w, nullptr, n_q, n_c, n_l, n_groups, ix->cand_cap, false);
+  if (need > kScratchBytes)
+    return fail(FR_EINVAL, "fr_search_noalloc: " + std::to_string(n_q) + " queries over " +
+                               std::to_string(n_groups) + " groups of 1024 documents need " +
+                               std::to_string(need >> 20) + " MiB of scratch, more than its " +
+                               std::to_string(kScratchBytes >> 20) + " MiB (use fewer queries, or fr_search)");
+  layout_workspace(ix, w, ix->scratch, n_q, n_c, n_l, n_groups, ix->cand_cap, false);
+  // the pinned input block is reused: the previous call's copy must be done
+  if (ix->na_pending) {
+    FR_HIP(hipEventSynchronize(ix->na_copied));
+    ix->na_pending = false;
+  }
+  layout_host_inputs(w, ix->na_h_in);
+  hipStream_t s = async ? (hipStream_t)stream : ix->stream;
+  w.h_desc[0] = n_q;
+  w.h_desc[1] = n_q;
+  w.h_desc[2] = 0;
+  w.h_desc[3] = 0;
+  std::memcpy(w.h_k, k, n_q * 4);
+  st = stage_inputs(ix, w, s, n_q, cnf, n_c, n_l);
+  if (st != FR_OK) return st;
+  FR_HIP(hipEventRecord(ix->na_copied, s));
+  ix->na_pending = true;
+  int qb = 1, nw = 4;
+  pick_tiling(ix, n_q, &qb, &nw);
+  const int gpi = pick_gpi(ix, n_q, 32 * qb * nw, n_groups);
+  st = enqueue_search(ix, w, s, qb, nw, gpi, n_groups, false, queries, out_ids, out_scores,
+                      out_count, (unsigned long long*)out_nmatch);
+  if (st != FR_OK) return st;
+  if (async) return FR_OK;
+  FR_HIP(hipMemcpyAsync(ix->na_h_count, out_count, (size_t)n_q * 4, hipMemcpyDeviceToHost, s));
+  FR_HIP(hipStreamSynchronize(s));
+  for (uint32_t q = 0; q < n_q; ++q)
+    if (ix->na_h_count[q] == 0xFFFFFFFFu)
+      return fail(FR_EUNSUPPORTED,
+                  "a query had more tied candidates than the candidate buffer holds (raise cand_cap)");
   return FR_OK;
 }
 
