@@ -20,6 +20,18 @@ constexpr int kMaxR = 4096;          // largest K / R handled by select and resc
 // matrix time of BF16 ones, so the quantised forms sample more
 constexpr int kSeedGroupsF32 = 32;
 constexpr int kSeedGroupsLow = 64;
+constexpr int kSeedGroupsMax = 128;
+constexpr int kSeedBins = 2048;      // histogram buckets of the sample's scores
+// starting-threshold sample: two kept scores per 16 documents of a tile
+constexpr int kSeedKeysMax = kSeedGroupsMax * (kGroup / kTile) * 4;
+// Speculative starting rank: with p the share of a query's matches that lie
+// in the sample, the number X of its K' best matches inside the sample is at
+// most Binomial(K', p) in the tails (hypergeometric), and Bernstein's
+// inequality gives P(X >= mu + t) <= exp(-t^2 / (2 (mu + t/3))), mu = K' p.
+// t solves that bound for exp(-kSpecL) (kSpecL = ln 10^4): the sample's r-th
+// best, r = mu + t + 1, is below the K'-th best of all matches except with
+// that probability, and a failure is detected after the pass.
+constexpr float kSpecL = 9.2103404f;
 constexpr int kLits = 12;            // literals per query in the scan's fast mask path
 // device scratch of fr_search_noalloc (one array per device, in the code
 // object) and the device ordinals it is looked up for
@@ -83,6 +95,7 @@ struct PrepArgs {
   const float* qnorm;      // per-query norm
   const uint32_t* norm_max;
   uint32_t* tau;
+  uint32_t* tsafe;         // safe starting key when the start is speculative, else 0
   uint32_t* cnt;
   uint32_t* smax;
   uint32_t* hist;
@@ -105,17 +118,22 @@ struct PrepArgs {
   uint32_t* linfo;
 };
 
-// Second pass for queries whose candidate buffer overflowed: keep their
-// (safe, tightened) threshold, narrow the histogram range to [tau, max seen]
-// and clear their counters.
+// Second pass for the queries the first one could not answer: those whose
+// candidate buffer overflowed keep their (safe, tightened) threshold with
+// the histogram range narrowed to [tau, max seen]; those whose speculative
+// starting threshold proved too high restart from the safe one.  Their
+// counters are cleared.
 struct RerunArgs {
   uint32_t max_q;
   const uint32_t* n_dev;
-  uint32_t* ovf;
+  uint32_t* ovf;           // 1: overflow, 2: speculative start too high
   uint32_t* qlist2;
   uint32_t* n_list2;
   const uint32_t* kp;
   uint32_t* tau;
+  uint32_t* tsafe;
+  const float* qnorm;
+  const uint32_t* norm_max;
   uint32_t* cnt;
   uint32_t* smax;
   uint32_t* hist;
@@ -150,7 +168,8 @@ struct MaskWordArgs {
 
 // Starting thresholds: for each query of the first pass, the K'-th best
 // score among the matches in the first few groups (less a rounding margin)
-// is a lower bound of its final K'-th best score.
+// is a lower bound of its final K'-th best score (the safe start); the r-th
+// best for a smaller r (see kSpecL) is a tighter, speculative start.
 struct SeedArgs {
   const uint32_t* qlist;
   const uint32_t* n_list;  // device
@@ -166,9 +185,11 @@ struct SeedArgs {
   uint32_t ppad;
   uint32_t n_groups;       // groups sampled (the first n_groups of the corpus)
   uint32_t dim;
-  uint32_t* skey;          // [max_list][row] sample score keys (scratch)
-  uint32_t row;            // skey row stride, >= n_groups * kGroup
+  uint32_t* skey;          // [list position][row] kept sample score keys (0: none)
+  uint32_t row;            // skey row stride, >= n_groups * 128
+  const unsigned long long* nmatch;   // matches of each query (whole corpus)
   uint32_t* tau;
+  uint32_t* tsafe;         // safe start when tau's start is speculative, else 0
   float* hlo;              // histogram range of the scan (narrowed here)
   float* hinvw;
 };
@@ -215,6 +236,7 @@ struct SelectArgs {
   uint32_t* sel_cnt;
   uint32_t rmax;
   uint32_t* ovf;
+  const uint32_t* tsafe;   // first pass: nonzero where the start was speculative
   // direct output (FP32 path)
   int write_out;
   const uint32_t* k;

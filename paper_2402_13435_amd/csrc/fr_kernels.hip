@@ -337,6 +337,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   }
   a.kp[q] = kp;
   a.tau[q] = kp ? kKeyNegInf : kKeyPosInf;
+  a.tsafe[q] = 0u;
   a.cnt[q] = 0u;
   a.smax[q] = 0u;
   a.nmatch[q] = 0ull;
@@ -379,6 +380,7 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
   FR_REQUIRE(a.qnorm);
   FR_REQUIRE(a.norm_max);
   FR_REQUIRE(a.tau);
+  FR_REQUIRE(a.tsafe);
   FR_REQUIRE(a.cnt);
   FR_REQUIRE(a.smax);
   FR_REQUIRE(a.hist);
@@ -404,14 +406,24 @@ __global__ __launch_bounds__(256) void k_rerun(RerunArgs a) {
   if (blockIdx.x == 0 && threadIdx.x < kXcds) a.work[threadIdx.x] = 0u;
   const uint32_t n_q = *a.n_dev;
   if (q >= n_q || q >= a.max_q || !a.ovf[q]) return;
+  const uint32_t why = a.ovf[q];
   a.ovf[q] = 0u;
   const uint32_t p = atomicAdd(a.n_list2, 1u);
   a.qlist2[p] = q;
-  // Raise the threshold from the complete first-pass histogram: the scan's
-  // own refreshes may have seen only part of it.  Same bucket rule (and
-  // one-bucket margin) as the scan's refresh.
   uint32_t* h = a.hist + (uint64_t)q * kHist;
-  {
+  float lo, hi;
+  if (why == 2u) {
+    // The speculative start was above the K'-th best score: every match at
+    // or above it was seen (the largest is smax), the rest lie below it.
+    // Scan again from the safe start.
+    hi = fmaxf(key2f(a.smax[q]), key2f(a.tau[q]));
+    a.tau[q] = a.tsafe[q];
+    lo = key2f(a.tsafe[q]);
+    if (!isfinite(lo)) lo = -(a.qnorm[q] * __uint_as_float(*a.norm_max) * 1.0001f);
+  } else {
+    // Raise the threshold from the complete first-pass histogram: the scan's
+    // own refreshes may have seen only part of it.  Same bucket rule (and
+    // one-bucket margin) as the scan's refresh.
     const uint32_t kp = a.kp[q];
     const float lo0 = a.hlo[q], iw0 = a.hinvw[q];
     uint32_t suffix = 0;
@@ -434,9 +446,10 @@ __global__ __launch_bounds__(256) void k_rerun(RerunArgs a) {
       const uint32_t nk = fkey(lo0 + (float)(bstar - 1) / iw0);
       if (nk > a.tau[q]) a.tau[q] = nk;
     }
+    lo = key2f(a.tau[q]);
+    hi = key2f(a.smax[q]);
   }
-  const float lo = key2f(a.tau[q]);
-  const float hi = key2f(a.smax[q]);
+  a.tsafe[q] = 0u;
   const float span = (hi - lo) * 1.0001f;
   const bool ok = span > 0.f && isfinite(span) && isfinite(lo);
   a.hlo[q] = ok ? lo : 0.f;
@@ -452,6 +465,9 @@ hipError_t launch_rerun(const RerunArgs& a, hipStream_t s) {
   FR_REQUIRE(a.n_list2);
   FR_REQUIRE(a.kp);
   FR_REQUIRE(a.tau);
+  FR_REQUIRE(a.tsafe);
+  FR_REQUIRE(a.qnorm);
+  FR_REQUIRE(a.norm_max);
   FR_REQUIRE(a.cnt);
   FR_REQUIRE(a.smax);
   FR_REQUIRE(a.hist);
@@ -487,29 +503,35 @@ __global__ __launch_bounds__(256) void k_mask_words(MaskWordArgs a) {
   unsigned long long cnt = 0;
   // words 2 part and 2 part + 1 of a 16-word run
   auto run2 = [&](const uint64_t* run) -> uint4 { return ((const uint4*)run)[part]; };
+  const bool fast = !empty && has && !slow;
   for (uint64_t g = g0; g < g1; ++g) {
     uint64_t m0 = 0ull, m1 = 0ull;
-    if (!empty) {
-      const uint4 v = run2(a.live + g * kWords);
-      m0 = ((uint64_t)v.y << 32) | v.x;
-      m1 = ((uint64_t)v.w << 32) | v.z;
-    }
+    const uint64_t* gb = a.bits + g * (uint64_t)a.vocab * kWords;
+    // the live run and every literal's run of the group, all loads in
+    // flight at once
+    uint4 lv = make_uint4(0u, 0u, 0u, 0u);
+    uint4 lw[kLits];
+    if (!empty) lv = run2(a.live + g * kWords);
+#pragma unroll
+    for (int i = 0; i < kLits; ++i)
+      lw[i] = (fast && i < (int)nlit) ? run2(gb + (uint64_t)tl[i] * kWords)
+                                      : make_uint4(0u, 0u, 0u, 0u);
+    m0 = ((uint64_t)lv.y << 32) | lv.x;
+    m1 = ((uint64_t)lv.w << 32) | lv.z;
     if (!empty && has) {
-      const uint64_t* gb = a.bits + g * (uint64_t)a.vocab * kWords;
       uint64_t c0 = 0ull, c1 = 0ull;
       if (!slow) {
-        for (uint32_t i = 0; i < nlit; ++i) {
-          if (i > 0 && ((starts >> i) & 1u)) {
-            m0 &= c0;
-            m1 &= c1;
-            c0 = c1 = 0ull;
-          }
-          uint32_t t = tl[0];
 #pragma unroll
-          for (int k = 1; k < kLits; ++k) t = (uint32_t)k == i ? tl[k] : t;
-          const uint4 v = run2(gb + (uint64_t)t * kWords);
-          c0 |= ((uint64_t)v.y << 32) | v.x;
-          c1 |= ((uint64_t)v.w << 32) | v.z;
+        for (int i = 0; i < kLits; ++i) {
+          if (i < (int)nlit) {
+            if (i > 0 && ((starts >> i) & 1u)) {
+              m0 &= c0;
+              m1 &= c1;
+              c0 = c1 = 0ull;
+            }
+            c0 |= ((uint64_t)lw[i].y << 32) | lw[i].x;
+            c1 |= ((uint64_t)lw[i].w << 32) | lw[i].z;
+          }
         }
         m0 &= c0;
         m1 &= c1;
@@ -748,11 +770,21 @@ __device__ __forceinline__ void read_scales(float4 (&xs)[4], const float* sslot,
 // corpus.  Step 1 scores every (sampled document, list position) pair with
 // the scan's own tile product (one wavefront per 32-document tile and
 // 32-position query block, the same instruction sequence as the scan, so
-// the scores match the scan's); step 2 keeps the matching documents of one
-// position and radix-selects its K'-th largest score.  The threshold is
-// still lowered by twice the FP32 summation bound gamma_d * |q| * max|x|
-// (12.5 % slack for the quantised forms' scaled norms), so it stays a lower
-// bound of the K'-th best final score whatever the accumulation order.
+// the scores match the scan's) and keeps, for every 16 documents of a tile
+// (one lane's accumulator rows), the two best matching scores: a subset of
+// the sample's matches.  Step 2 reads two ranks off each query's subset
+// through a histogram of its scores:
+//   * the K'-th best, a lower bound of the K'-th best match of the corpus
+//     (the K'-th best of any subset of the matches is at most the K'-th
+//     best of all of them): the safe start;
+//   * the r-th best for the r of kSpecL (the speculative start, used when
+//     r < K'): below the corpus's K'-th best except with probability about
+//     10^-4 by the bound, about 10^-6 in fact; if a pass collects fewer than
+//     min(K', n_match) candidates from it, the query is scanned again from
+//     the safe start, so the result stays exact.
+// Both are read from bucket edges and lowered by twice the FP32 summation
+// bound gamma_d * |q| * max|x| (12.5 % slack for the quantised forms'
+// scaled norms), so they stay lower bounds whatever the accumulation order.
 template <int DT, int DPAD>
 __global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
   constexpr int ES = DT == kF32 ? 4 : DT == kBF16 ? 2 : 1;
@@ -777,123 +809,139 @@ __global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
   for (int v = 0; v < 16; ++v) acc[0][v] = 0.f;
   mma_tile<DT, CH, 1>(acc, a.tiles + (uint64_t)t * (CH * 1024), bq, lane);
   if (!qv) return;
+  // predicate bits of the tile's 32 documents for this query (tile t is
+  // tile t % 32 of group t / 32: half of mask word (t % 32) / 2)
+  const uint32_t g = t / (uint32_t)(kGroup / kTile), tg = t % (uint32_t)(kGroup / kTile);
+  const uint64_t mword = a.mw[((uint64_t)g * kWords + (tg >> 1)) * a.ppad + pos];
+  const uint32_t mrow = (uint32_t)(mword >> ((tg & 1u) * 32u)) >> (4 * half);
   const float qs = DT == kFP8 ? a.qscale[q] : 1.f;
-  uint32_t* out = a.skey + (uint64_t)pos * a.row + (uint64_t)t * kTile;
+  // the two best keys among this lane's matching rows (0: none)
+  uint32_t k1 = 0u, k2 = 0u;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    uint32_t k4[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      float sc = acc[0][4 * g + e];
-      if constexpr (DT == kFP8) sc = (sc * qs) * a.xscale[(uint64_t)t * kTile + acc_row(4 * g + e, half)];
-      k4[e] = fkey(sc);
-    }
-    *(uint4*)(out + 8 * g + 4 * half) = make_uint4(k4[0], k4[1], k4[2], k4[3]);
+  for (int v = 0; v < 16; ++v) {
+    float sc = acc[0][v];
+    if constexpr (DT == kFP8) sc = (sc * qs) * a.xscale[(uint64_t)t * kTile + acc_row(v, half)];
+    const uint32_t key = ((mrow >> (8 * (v >> 2) + (v & 3))) & 1u) ? fkey(sc) : 0u;
+    const uint32_t lo = min(k1, key);
+    k1 = max(k1, key);
+    k2 = max(k2, lo);
   }
+  *(uint2*)(a.skey + (uint64_t)pos * a.row + (uint64_t)t * 4u + 2u * (uint32_t)half) =
+      make_uint2(k1, k2);
 }
 
-constexpr int kSelThreads = 1024;   // one workgroup per query, 16 wavefronts
-__global__ __launch_bounds__(kSelThreads) void k_seed_select(SeedArgs a) {
-  // The matching documents' keys are compacted into LDS, at most kCap of
-  // them: the K'-th largest of any subset of the matches is still at most
-  // the K'-th largest of all, so a full buffer only loosens the bound.
-  constexpr uint32_t kCap = 16384;
-  __shared__ uint32_t s_key[kCap];
-  __shared__ uint32_t s_hist[256];
-  __shared__ uint32_t s_n, s_digit, s_rank;
+// Bucket of a per-query histogram (kSeedBins counters, lane l holding
+// buckets 32 l .. 32 l + 31 in c) where the count from the top first
+// reaches `rank`; -1 if the histogram holds fewer.  Wave-uniform.
+__device__ __forceinline__ int seed_rank_bucket(const uint32_t (&c)[32], uint32_t lane_sum,
+                                                uint32_t suffix_incl, uint32_t rank, int lane) {
+  const uint32_t above = suffix_incl - lane_sum;   // counts in higher lanes
+  int found = -1;
+  if (rank > 0u && above < rank && rank <= suffix_incl) {
+    uint32_t run = above;
+    for (int e = 31; e >= 0; --e) {
+      run += c[e];
+      if (run >= rank) {
+        found = 32 * lane + e;
+        break;
+      }
+    }
+  }
+  const uint64_t bal = __ballot(found >= 0);     // one lane at most
+  if (!bal) return -1;
+  return __shfl(found, __builtin_ctzll(bal));
+}
+
+// One workgroup per list position: the kept sample scores go into a
+// histogram of kSeedBins buckets over [-|q| max|x|, +|q| max|x|] in LDS (the
+// paper's bucket top-K, appendix "Fast Top K Selection", with the
+// Cauchy-Schwarz range standing in for the known score bounds); each
+// starting threshold is the lower edge of the bucket below the one where its
+// rank is reached, so it is at most the rank's score.  The scan's histogram
+// range is narrowed to [start, |q| max|x|].
+constexpr int kSeedSelThreads = 256;
+__global__ __launch_bounds__(kSeedSelThreads) void k_seed_select(SeedArgs a) {
+  __shared__ uint32_t s_hist[kSeedBins];
+  __shared__ uint32_t s_ms;
   const int tid = threadIdx.x, lane = tid & 63;
   const uint32_t pos = blockIdx.x;
   if (pos >= *a.n_list || pos >= a.max_list) return;
   const uint32_t q = a.qlist[pos];
   const uint32_t kp = a.kp[q];
-  const uint32_t nd = a.n_groups * (uint32_t)kGroup;
-  if (kp == 0u || kp > nd || kp > kCap) return;
-  if (tid == 0) s_n = 0u;
+  const float bound = a.qnorm[q] * __uint_as_float(*a.norm_max);
+  const float hi = bound * 1.0001f;
+  if (kp == 0u || !(hi > 0.f) || !isfinite(hi)) return;
+  const float w = (float)kSeedBins / (2.f * hi);
+  for (int i = tid; i < kSeedBins; i += kSeedSelThreads) s_hist[i] = 0u;
+  if (tid == 0) s_ms = 0u;
   __syncthreads();
-  // runs of 16 documents, thread t taking runs t, t + kSelThreads, ...
-  for (uint32_t i0 = (uint32_t)tid * 16u; i0 < nd; i0 += kSelThreads * 16u) {
-    const uint32_t bits = (uint32_t)(a.mw[(uint64_t)(i0 / 64u) * a.ppad + pos] >> (i0 % 64u)) & 0xFFFFu;
-    if (!bits) continue;
-    const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * a.row + i0);
-    uint32_t kk[16];
+  // the kept scores (key 0: none) and the sample's matches
+  const uint32_t n = a.n_groups * (uint32_t)(kGroup / kTile) * 4u;
+  const uint4* src = (const uint4*)(a.skey + (uint64_t)pos * a.row);
+  for (uint32_t i = (uint32_t)tid; i < n / 4u; i += kSeedSelThreads) {
+    const uint4 v = src[i];
+    const uint32_t k4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const uint4 v = src[c];
-      kk[4 * c] = v.x;
-      kk[4 * c + 1] = v.y;
-      kk[4 * c + 2] = v.z;
-      kk[4 * c + 3] = v.w;
+    for (int e = 0; e < 4; ++e) {
+      if (!k4[e]) continue;
+      const float fb = (key2f(k4[e]) + hi) * w;
+      const int bk = fb >= (float)(kSeedBins - 1) ? kSeedBins - 1 : (fb > 0.f ? (int)fb : 0);
+      atomicAdd(&s_hist[bk], 1u);
     }
-    uint32_t at = atomicAdd(&s_n, (uint32_t)__builtin_popcount(bits));
-#pragma unroll
-    for (int e = 0; e < 16; ++e)
-      if ((bits >> e) & 1u) {
-        if (at < kCap) s_key[at] = kk[e];
-        ++at;
-      }
   }
+  uint32_t ms = 0u;
+  for (uint32_t i = (uint32_t)tid; i < a.n_groups * (uint32_t)kWords; i += kSeedSelThreads)
+    ms += (uint32_t)__popcll(a.mw[(uint64_t)i * a.ppad + pos]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) ms += __shfl_xor(ms, off);
+  if (lane == 0 && ms) atomicAdd(&s_ms, ms);
   __syncthreads();
-  const uint32_t n = s_n < kCap ? s_n : kCap;
-  if (n < kp) return;   // uniform: too few matches in the sample
-  // most-significant-byte-first radix select of the kp-th largest key
-  uint32_t prefix = 0u, pmask = 0u, rank = kp;
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    if (tid < 256) s_hist[tid] = 0u;
-    __syncthreads();
-    for (uint32_t i = (uint32_t)tid; i < n; i += kSelThreads) {
-      const uint32_t k = s_key[i];
-      if ((k & pmask) == prefix) atomicAdd(&s_hist[(k >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    if (tid < 64) {
-      // lane l holds digits 4l..4l+3; suffix sums over lanes find the digit
-      // d with (count above d) < rank <= (count at or above d)
-      uint32_t h[4], c = 0u;
+  if (tid >= 64) return;
+  ms = s_ms;
+  uint32_t c[32], sum = 0u;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        h[e] = s_hist[4 * lane + e];
-        c += h[e];
-      }
-      uint32_t suf = c;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = __shfl_down(suf, off, 64);
-        if (lane + off < 64) suf += o;
-      }
-      uint32_t above = suf - c;
-      if (above < rank && rank <= suf) {
-        for (int e = 3; e >= 0; --e) {
-          if (above + h[e] >= rank) {
-            s_digit = 4u * (uint32_t)lane + (uint32_t)e;
-            s_rank = rank - above;
-            break;
-          }
-          above += h[e];
-        }
-      }
-    }
-    __syncthreads();
-    prefix |= s_digit << shift;
-    pmask |= 255u << shift;
-    rank = s_rank;
-    __syncthreads();
+  for (int e = 0; e < 32; ++e) {
+    c[e] = s_hist[32 * lane + e];
+    sum += c[e];
   }
-  if (tid == 0) {
-    const float u = 5.9604644775390625e-8f;   // 2^-24
-    const float dd = (float)a.dim;
-    const float gam = dd * u / (1.f - dd * u);
-    const float bound = a.qnorm[q] * __uint_as_float(*a.norm_max);
-    const float tol = 2.f * gam * bound * 1.125f + 1e-30f;
-    const float tv = key2f(prefix) - tol;
-    atomicMax(a.tau + q, fkey(tv));
-    // every candidate of the scan scores at least tv: the histogram range
-    // shrinks to [tv, hi], so its buckets (and the thresholds read from it)
-    // are finer
-    const float hi = bound * 1.0001f;
-    if (isfinite(tv) && tv < hi && isfinite(hi)) {
-      a.hlo[q] = tv;
-      a.hinvw[q] = (float)kNBF / (hi - tv);
-    }
+  // inclusive suffix sum over lanes (higher lanes hold higher scores)
+  uint32_t suf = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_down(suf, off, 64);
+    if (lane + off < 64) suf += o;
+  }
+  // speculative rank from the Bernstein bound (see kSpecL), p = the share
+  // of the query's matches that lie in the sample
+  uint32_t r = kp;
+  const double m_all = (double)a.nmatch[q];
+  if (m_all > 0.0 && ms > 0u) {
+    const float p = fminf(1.f, (float)((double)ms / m_all));
+    const float mu = (float)kp * p;
+    const float l3 = 2.f * kSpecL / 3.f;
+    const float t = 0.5f * (l3 + sqrtf(l3 * l3 + 8.f * kSpecL * mu));
+    const float rf = floorf(mu + t) + 1.f;
+    if (rf < (float)kp) r = (uint32_t)rf;
+  }
+  const int b_safe = seed_rank_bucket(c, sum, suf, kp, lane);
+  const int b_spec = r < kp ? seed_rank_bucket(c, sum, suf, r, lane) : -1;
+  if (lane != 0) return;
+  const float u = 5.9604644775390625e-8f;   // 2^-24
+  const float dd = (float)a.dim;
+  const float gam = dd * u / (1.f - dd * u);
+  const float tol = 2.f * gam * bound * 1.125f + 1e-30f;
+  auto edge = [&](int b) -> float { return -hi + (float)(b - 1) / w - tol; };
+  const float t_safe = b_safe >= 0 ? edge(b_safe) : -INFINITY;
+  const float t_spec = b_spec >= 0 ? edge(b_spec) : -INFINITY;
+  const float start = fmaxf(t_safe, t_spec);
+  if (!(start > -INFINITY)) return;            // too few matches in the sample
+  atomicMax(a.tau + q, fkey(start));
+  a.tsafe[q] = start > t_safe ? fkey(t_safe) : 0u;
+  // every candidate of the scan scores at least `start`: the histogram
+  // range shrinks to [start, hi], so its buckets are finer
+  if (start < hi) {
+    a.hlo[q] = start;
+    a.hinvw[q] = (float)kNBF / (hi - start);
   }
 }
 
@@ -912,7 +960,9 @@ hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s) {
   FR_REQUIRE(a.norm_max);
   FR_REQUIRE(a.mw);
   FR_REQUIRE(a.skey);
+  FR_REQUIRE(a.nmatch);
   FR_REQUIRE(a.tau);
+  FR_REQUIRE(a.tsafe);
   FR_REQUIRE(a.hlo);
   FR_REQUIRE(a.hinvw);
   if (dt == kFP8) {
@@ -920,14 +970,18 @@ hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s) {
     FR_REQUIRE(a.qscale);
   }
   if (a.max_list == 0 || a.n_groups == 0) return hipSuccess;
-  if ((uint64_t)a.n_groups * kGroup > a.row || a.row % 16u) return hipErrorInvalidValue;
+  if (a.ppad < a.max_list) return hipErrorInvalidValue;
+  // four kept keys per sampled tile, all of them held in LDS by the select
+  if ((uint64_t)a.n_groups * (kGroup / kTile) * 4u > a.row || a.row % 4u ||
+      (uint64_t)a.n_groups * (kGroup / kTile) * 4u > (uint64_t)kSeedKeysMax)
+    return hipErrorInvalidValue;
   const uint32_t ng = a.n_groups;
   const dim3 g1((ng * (kGroup / kTile) + 3u) / 4u, (a.max_list + kTile - 1u) / kTile);
 #define FR_SEED(D, P)                                                  \
   if (dt == D && dpad == P) {                                          \
     hipLaunchKernelGGL((k_seed_scores<D, P>), g1, dim3(256), 0, s, a); \
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;   \
-    hipLaunchKernelGGL(k_seed_select, dim3(a.max_list), dim3(kSelThreads), 0, s, a); \
+    hipLaunchKernelGGL(k_seed_select, dim3(a.max_list), dim3(kSeedSelThreads), 0, s, a); \
     return hipGetLastError();                                          \
   }
   FR_SEED_CASES(FR_SEED)
@@ -1537,9 +1591,19 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
             }
           }
           const f32x16& s = acc;
-          float mx = s[0];
+          // largest score among the lane's rows that satisfy the predicate:
+          // a row's mask bit, sign-extended, selects its score or -inf, so
+          // the candidate step below runs only when a matching row reaches
+          // the threshold
+          const uint32_t mrow = m32 >> (4 * half);
+          float mx = -INFINITY;
 #pragma unroll
-          for (int v = 1; v < 16; ++v) mx = fmaxf(mx, s[v]);
+          for (int v = 0; v < 16; ++v) {
+            const uint32_t sel = (uint32_t)__builtin_amdgcn_sbfe(
+                (int)mrow, 8 * (v >> 2) + (v & 3), 1);
+            const uint32_t bits = (__float_as_uint(s[v]) & sel) | (0xFF800000u & ~sel);
+            mx = fmaxf(mx, __uint_as_float(bits));
+          }
           const bool cand = (m32 != 0u) && (mx >= thr[b]);
           if (__ballot(cand)) {
             // mask bits of the lane's 16 accumulator rows: row 8g + 4 half + i
@@ -1722,6 +1786,16 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     }
     return;
   }
+  if (!a.final_pass && a.tsafe[q] != 0u && (unsigned long long)c < min((unsigned long long)kp, a.nmatch[q])) {
+    // The speculative starting threshold was above the K'-th best match
+    // (fewer candidates than min(K', matches) reached it): scan again from
+    // the safe one.
+    if (threadIdx.x == 0) {
+      a.ovf[q] = 2u;
+      a.sel_cnt[q] = 0u;
+    }
+    return;
+  }
   const uint32_t tau = a.tau[q];
   const unsigned long long* ck = a.cand_key + (uint64_t)q * a.cap;
   // a candidate is stored as (score key, slot); its sort key is (score key,
@@ -1831,6 +1905,8 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
   FR_REQUIRE(a.sel_slot);
   FR_REQUIRE(a.sel_cnt);
   FR_REQUIRE(a.ovf);
+  FR_REQUIRE(a.tsafe);
+  FR_REQUIRE(a.nmatch);
   if (a.rmax > (uint32_t)kMaxR || a.rmax < 1) return hipErrorInvalidValue;
   if (a.write_out) {
     FR_REQUIRE(a.k);
@@ -1870,25 +1946,36 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
                        : make_float4(0.f, 0.f, 0.f, 0.f);
   const unsigned long long* sk = a.sel_key + (uint64_t)q * a.rmax;
   const uint32_t* ss = a.sel_slot + (uint64_t)q * a.rmax;
-  for (uint32_t r0 = wave * 4; r0 < m; r0 += 16) {
-    float4 xv[4];
+  // wavefront `wave` rescores rows [rb, re): their slots and ids are read
+  // 64 at a time (one per lane), then 16 rows are gathered at once
+  const uint32_t per = (m + 3u) / 4u;
+  const uint32_t rb = min(m, (uint32_t)wave * per), re = min(m, rb + per);
+  for (uint32_t c0 = rb; c0 < re; c0 += 64u) {
+    const uint32_t nr = min(64u, re - c0);
+    const uint32_t my_slot = (uint32_t)lane < nr ? ss[c0 + lane] : 0u;
+    const uint32_t my_id = (uint32_t)lane < nr ? (uint32_t)sk[c0 + lane] : 0u;
+    for (uint32_t j0 = 0; j0 < nr; j0 += 16u) {
+      float4 xv[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t r = r0 + u;
-      xv[u] = (on && r < m) ? *((const float4*)(a.master + (uint64_t)ss[r] * a.dpad) + lane)
-                            : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+      for (int u = 0; u < 16; ++u) {
+        const uint32_t j = j0 + (uint32_t)u;
+        const uint32_t slot = (uint32_t)__shfl((int)my_slot, (int)(j & 63u));
+        xv[u] = (on && j < nr) ? *((const float4*)(a.master + (uint64_t)slot * a.dpad) + lane)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      float p = xv[u].x * qv.x;
-      p = fmaf(xv[u].y, qv.y, p);
-      p = fmaf(xv[u].z, qv.z, p);
-      p = fmaf(xv[u].w, qv.w, p);
+      for (int u = 0; u < 16; ++u) {
+        float p = xv[u].x * qv.x;
+        p = fmaf(xv[u].y, qv.y, p);
+        p = fmaf(xv[u].z, qv.z, p);
+        p = fmaf(xv[u].w, qv.w, p);
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) p += __shfl_xor(p, off);
-      const uint32_t r = r0 + u;
-      if (lane == 0 && r < m)
-        s_key[r] = ((unsigned long long)fkey(p) << 32) | (sk[r] & 0xFFFFFFFFull);
+        for (int off = 1; off < 64; off <<= 1) p += __shfl_xor(p, off);
+        const uint32_t j = j0 + (uint32_t)u;
+        const uint32_t id = (uint32_t)__shfl((int)my_id, (int)(j & 63u));
+        if (lane == 0 && j < nr)
+          s_key[c0 + j] = ((unsigned long long)fkey(p) << 32) | (unsigned long long)id;
+      }
     }
   }
   const int n2 = pow2_at_least((int)(m ? m : 1));

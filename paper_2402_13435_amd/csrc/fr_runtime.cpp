@@ -67,9 +67,8 @@ uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 
 struct Workspace {
   // sizes the buffers below were laid out for: queries, clauses and
-  // literals per search, row stride of the masks, candidate slots per
-  // query, row stride of the starting-threshold sample
-  uint32_t qcap = 0, cmax = 0, lmax = 0, ppad = 0, cand_cap = 0, seed_row = 0;
+  // literals per search, row stride of the masks, candidate slots per query
+  uint32_t qcap = 0, cmax = 0, lmax = 0, ppad = 0, cand_cap = 0;
   // device
   float* qrow = nullptr;
   uint8_t* qtiles = nullptr;
@@ -100,7 +99,8 @@ struct Workspace {
   unsigned long long* nmatch = nullptr;
   unsigned long long* cand_key = nullptr;
   uint64_t* mw = nullptr;    // predicate masks of the current pass
-  uint32_t* skey = nullptr;  // sample score keys of the starting thresholds
+  uint32_t* skey = nullptr;   // kept sample scores of the starting thresholds
+  uint32_t* tsafe = nullptr;  // safe starting thresholds behind speculative ones
   unsigned long long* sel_key = nullptr;
   uint32_t* sel_slot = nullptr;
   uint32_t* out_ids = nullptr;
@@ -194,6 +194,10 @@ struct fr_index {
 
 namespace {
 
+// row stride (keys) of a workspace's starting-threshold sample: four kept
+// scores per sampled tile
+uint32_t seed_row(const fr_index* ix) { return ix->seed_groups * (kGroup / kTile) * 4u; }
+
 template <class T>
 void carve(T** p, uint8_t* base, size_t& off, size_t count) {
   *p = base ? (T*)(base + off) : nullptr;
@@ -213,7 +217,6 @@ size_t layout_workspace(const fr_index* ix, Workspace& w, uint8_t* base, uint32_
   w.lmax = lm;
   w.ppad = round_up(std::max<uint32_t>(qm, 1), 256);
   w.cand_cap = cand_cap;
-  w.seed_row = ix->seed_groups * kGroup;
   const size_t tb = tile_bytes(ix->dt, ix->dpad);
   size_t off = 0;
   carve(&w.qrow, base, off, (size_t)qm * ix->dpad);
@@ -245,7 +248,8 @@ size_t layout_workspace(const fr_index* ix, Workspace& w, uint8_t* base, uint32_
   carve(&w.hinvw, base, off, qm);
   carve(&w.nmatch, base, off, qm);
   carve(&w.cand_key, base, off, (size_t)qm * cand_cap);
-  carve(&w.skey, base, off, (size_t)qm * w.seed_row);
+  carve(&w.skey, base, off, (size_t)qm * seed_row(ix));
+  carve(&w.tsafe, base, off, qm);
   // the scan's padding loads read the first 4096 words of the masks
   carve(&w.mw, base, off, std::max<size_t>((size_t)n_groups * kWords * w.ppad, 4096));
   carve(&w.sel_key, base, off, (size_t)qm * ix->rmax);
@@ -432,6 +436,7 @@ PrepArgs prep_args(const fr_index* ix, Workspace& w) {
   pa.qnorm = w.qnorm;
   pa.norm_max = ix->norm_max;
   pa.tau = w.tau;
+  pa.tsafe = w.tsafe;
   pa.cnt = w.cnt;
   pa.smax = w.smax;
   pa.hist = w.hist;
@@ -513,10 +518,12 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sd.mw = w.mw;
   sd.ppad = ma.ppad;
   sd.n_groups = std::min(n_groups, ix->seed_groups);
-  sd.row = w.seed_row;
   sd.dim = ix->dim;
   sd.skey = w.skey;
+  sd.row = seed_row(ix);
+  sd.nmatch = w.nmatch;
   sd.tau = w.tau;
+  sd.tsafe = w.tsafe;
   sd.hlo = w.hlo;
   sd.hinvw = w.hinvw;
   FR_HIP(launch_seed(sd, ix->dt, ix->dpad, s));
@@ -565,6 +572,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   se.sel_cnt = w.sel_cnt;
   se.rmax = ix->rmax;
   se.ovf = w.ovf;
+  se.tsafe = w.tsafe;
   se.write_out = ix->dt == kF32;
   se.k = w.k;
   se.k_max = ix->cfg.k_max;
@@ -584,6 +592,9 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   ra.n_list2 = w.desc + 2;
   ra.kp = w.kp;
   ra.tau = w.tau;
+  ra.tsafe = w.tsafe;
+  ra.qnorm = w.qnorm;
+  ra.norm_max = ix->norm_max;
   ra.cnt = w.cnt;
   ra.smax = w.smax;
   ra.hist = w.hist;

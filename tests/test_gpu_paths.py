@@ -9,6 +9,8 @@ the FP64 oracle:
 * the exact selection's radix-select fallback (more than 8192 candidates at
   or above the final threshold, from a block of tied scores);
 * thresholds over negative scores (the histogram spans [-|q| max|x|, +...]);
+* a speculative starting threshold that proves too high (second pass from
+  the safe one);
 * the failure marker of a query that cannot be answered, on synchronous,
   device-pointer and asynchronous searches.
 """
@@ -220,6 +222,66 @@ def test_negative_scores_raise_the_threshold():
     for i in range(2):
         check_query(o, batch, i, res, 16)
         assert np.all(res.scores[i, :16] < 0)
+    ix.close()
+
+
+def _front_loaded_corpus(n_groups=320, d=64, seed=13):
+    """Scores against e_0: spread over 0.5..0.99 in the first 64 groups (the
+    starting-threshold sample of every dtype), over -0.3..0.3 elsewhere.
+    Terms: every document has term 0; one in three also has term 1."""
+    rng = np.random.default_rng(seed)
+    n = n_groups * 1024
+    x = rng.standard_normal((n, d))
+    x[:, 0] = 0.0
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    s = np.where(np.arange(n) < 64 * 1024, rng.uniform(0.5, 0.99, n), rng.uniform(-0.3, 0.3, n))
+    x = x * np.sqrt(1.0 - s ** 2)[:, None]
+    x[:, 0] = s
+    lists = [[0, 1] if i % 3 == 0 else [0] for i in range(n)]
+    off = np.cumsum([0] + [len(t) for t in lists]).astype(np.int64)
+    terms = np.concatenate([np.asarray(t, np.uint32) for t in lists])
+    cfg = datagen.scaled(datagen.CONFIGS["tiny"], n, 4)
+    return SimpleNamespace(emb=x.astype(np.float32), ids=(np.arange(n, dtype=np.uint32) * 5 + 2),
+                           term_off=off, terms=terms, n=n, cfg=cfg)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_speculative_start_falls_back_to_the_safe_one(dtype):
+    """The starting threshold is first the sample's r-th best score for an r
+    well below K' (the sample holds a tenth to a fifth of the matches).  Here
+    every top-K' document lies in the sample, so that start is above the
+    K'-th best: the first pass collects fewer than K' candidates, and the
+    query is scanned again from the safe start (the sample's K'-th best).
+    The query ranking the other way (-e_0) and a K=0 query in the same batch
+    need no second pass; all of them match the oracle."""
+    c = _front_loaded_corpus()
+    o = oracle_for(c)
+    kw = dict(rescore_r=400) if dtype == "bf16" else {}
+    ix = gpu_index(c, k_max=100, dtype=dtype, **kw)
+    q = np.zeros((4, c.cfg.dim), np.float32)
+    q[0, 0] = q[2, 0] = q[3, 0] = 1.0
+    q[1, 0] = -1.0
+    batch = datagen.from_cnf_lists(q, [[], [], [[1]], []], [100, 100, 100, 0])
+    res = ix.search(q, batch, batch.k)
+    st = ix.stats()
+    print(f"[paths] speculative fallback ({dtype}): {st.n_passes} passes, "
+          f"{st.candidates} candidates", flush=True)
+    assert st.n_passes == 2
+    if dtype == "f32":
+        for i in range(4):
+            check_query(o, batch, i, res, int(batch.k[i]))
+    else:
+        # with q = +-e_0 a document's BF16 first-pass score is exactly
+        # bf16(x_0), so the oracle's emulation of the pipeline (top 400 by
+        # (approximate desc, id asc), FP32 rescoring, top 100) gives the ids
+        tol = tolerance(c.cfg.dim)
+        for i in range(4):
+            k = int(batch.k[i])
+            a = o.search_rescored_one(q[i], batch.cnf(i), k, 400, "bf16")
+            cnt = int(res.count[i])
+            assert cnt == a.count and int(res.n_match[i]) == a.n_match, i
+            assert np.array_equal(res.ids[i, :cnt], a.ids), i
+            assert np.all(np.abs(res.scores[i, :cnt] - a.scores) <= tol), i
     ix.close()
 
 
