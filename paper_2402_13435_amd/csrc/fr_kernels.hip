@@ -26,6 +26,7 @@
 //    literals' runs; the CNF is the AND of the clauses (appendix, "TBR").
 //  * live bits and slot ids per document slot.
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 
@@ -680,18 +681,33 @@ __device__ __forceinline__ int acc_row(int v, int h) { return 8 * (v >> 2) + 4 *
 // loads.  Keeping the tile loads on their own wavefront keeps them out of
 // the compute wavefronts' memory counters, so candidate atomics and mask
 // loads there never wait behind tile traffic.
-template <int DT, int DPAD>
+// Geometry of the scan's LDS ring.  A slot is one hand-over between the
+// loader and the compute wavefronts: TPS consecutive tiles of one group
+// (more documents per hand-over for the smaller tiles of the reduced
+// precisions), the predicate-mask words of those tiles for the work item's
+// QT queries ([word][QT] u64; a word covers two tiles), and for FP8 the
+// tiles' row scales.
+constexpr int kRingBytes = 112 * 1024;
+template <int DT, int DPAD, int QT>
 struct Ring {
   static constexpr int ES = DT == kF32 ? 4 : DT == kBF16 ? 2 : 1;
   static constexpr int CH = DPAD * ES / 32;   // 1 KB chunks per tile
   static constexpr int TB = CH * 1024;       // tile bytes
-  static constexpr int L = CH + (DT == kFP8 ? 1 : 0);   // loads per tile
-  // tiles in flight ahead of the one being scored: about 64 KB of ring,
-  // at least 2, at most 8, and within the 6-bit memory counter
-  static constexpr int PD0 = 65536 / TB - 1;
-  static constexpr int PD1 = PD0 < 2 ? 2 : PD0 > 8 ? 8 : PD0;
-  static constexpr int PD = (PD1 - 1) * L <= 63 ? PD1 : 63 / L + 1;
+  static constexpr int TPS = TB > 16384 ? 1 : TB > 8192 ? 2 : 4;   // tiles per slot
+  static constexpr int WPC = TPS >= 2 ? TPS / 2 : 1;               // mask words per slot
+  static constexpr int LM = QT / 128;        // 1 KB loads per mask word
+  static constexpr int MOFF = TPS * TB;      // offset of the mask words
+  static constexpr int SOFF = MOFF + WPC * QT * 8;   // offset of the FP8 scales
+  static constexpr int SB = SOFF + (DT == kFP8 ? TPS * kTile * 4 : 0);   // slot bytes
+  static constexpr int LS = TPS * (CH + (DT == kFP8 ? 1 : 0)) + WPC * LM;   // loads per slot
+  // slots in flight ahead of the one being scored: as many as the ring's
+  // LDS share holds, within the 6-bit memory counter
+  static constexpr int PDV = 63 / LS + 1;
+  static constexpr int PDL = kRingBytes / SB - 1;
+  static constexpr int PD = PDV < PDL ? PDV : PDL;
   static constexpr int NS = PD + 1;          // slots
+  static_assert(PD >= 1 && (PD - 1) * LS <= 63, "ring geometry");
+  static_assert(QT % 128 == 0 && SB % 16 == 0, "ring layout");
 };
 
 __device__ __forceinline__ constexpr int vm_wait_code(int n) {
@@ -742,13 +758,13 @@ __device__ __forceinline__ void dma_tile(const uint8_t* __restrict__ tiles,
   }
 }
 
-// Wait until at most `younger` tiles' loads of this wavefront are in flight.
+// Wait until at most `younger` slots' loads of this wavefront are in flight.
 template <int L, int PD>
-__device__ __forceinline__ void wait_tiles(uint32_t younger) {
+__device__ __forceinline__ void wait_slots(uint32_t younger) {
   static_assert((PD - 1) * L <= 63, "memory counter range");
   switch (younger) {
     case 0: __builtin_amdgcn_s_waitcnt(vm_wait_code(0)); break;
-    case 1: __builtin_amdgcn_s_waitcnt(vm_wait_code(1 * L)); break;
+    case 1: if constexpr (PD > 1) { __builtin_amdgcn_s_waitcnt(vm_wait_code(1 * L)); break; }
     case 2: if constexpr (PD > 2) { __builtin_amdgcn_s_waitcnt(vm_wait_code(2 * L)); break; }
     case 3: if constexpr (PD > 3) { __builtin_amdgcn_s_waitcnt(vm_wait_code(3 * L)); break; }
     case 4: if constexpr (PD > 4) { __builtin_amdgcn_s_waitcnt(vm_wait_code(4 * L)); break; }
@@ -1057,25 +1073,20 @@ __device__ __forceinline__ uint64_t mask_combine(const MaskJob& j, uint32_t info
 // item set-up, one at the item end.
 template <int DT, int DPAD, int QB, int NW>
 __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
-  using R = Ring<DT, DPAD>;
-  constexpr int CH = R::CH;                 // 16-byte chunks per lane per tile
   constexpr int QT = NW * QB * 32;          // queries per work item
-  constexpr int LM = QT / 128;              // 1 KB mask loads per word (and per tile)
-  constexpr int LT = R::L + LM;             // loader's loads per tile
-  // tiles in flight: the ring's choice, within the 6-bit memory counter
-  constexpr int PD = (R::PD - 1) * LT <= 63 ? R::PD : 63 / LT + 1;
-  constexpr int NS = PD + 1;                // ring slots
+  using R = Ring<DT, DPAD, QT>;
+  constexpr int CH = R::CH;                 // 16-byte chunks per lane per tile
+  constexpr int TPS = R::TPS;               // tiles per ring slot
+  constexpr int SPG = (kGroup / kTile) / TPS;   // slots per group
+  constexpr int PD = R::PD;                 // slots in flight
+  constexpr int NS = R::NS;                 // ring slots
   constexpr int SR = NW > 4 ? 256 : 512;    // staging ring entries per wavefront
   constexpr long long kPeriod = 3000;       // keeper period, shader clocks
   constexpr int RJ = QT / 64;               // queries per keeper lane
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   static_assert(QT <= 256, "staged query index is one byte");
   static_assert(NW % 4 == 0, "done counters are read four at a time");
-  __shared__ __attribute__((aligned(16))) uint8_t s_ring[NS * R::TB];
-  __shared__ __attribute__((aligned(16))) float s_rscale[DT == kFP8 ? NS * kTile : 4];
-  // predicate masks of the current and the next group: [group % 2][word][j]
-  __shared__ __attribute__((aligned(16))) uint64_t s_mask[2][kWords][QT];
-  __shared__ __attribute__((aligned(16))) uint8_t s_msink[LM * 1024];   // target of padding loads
+  __shared__ __attribute__((aligned(16))) uint8_t s_ring[NS * R::SB];
   __shared__ uint32_t s_item;
   // per query of the item, index j = (wave * QB + b) * 32 + col
   __shared__ float s_thr[QT];
@@ -1083,8 +1094,8 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   __shared__ uint32_t s_qkp[QT];            // selection size
   __shared__ float s_qlo[QT];
   __shared__ float s_qiw[QT];
-  // ring hand-over: sequence number of the tile in each slot, tiles done
-  // per compute wavefront (sequence numbers run on across items)
+  // ring hand-over: sequence number of the slot load in each slot, slot
+  // loads done per compute wavefront (sequence numbers run on across items)
   __shared__ uint32_t s_ready[NS];
   __shared__ __attribute__((aligned(16))) uint32_t s_done[NW];
   __shared__ uint32_t s_fin[NW];            // item number a compute wavefront finished
@@ -1133,11 +1144,13 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
 
   if (wave == NW) {
     // ---------------------------------------------------------- loader
-    // Tile seq goes to slot seq % NS.  It is issued once every compute
-    // wavefront is done with the slot's previous tile (seq - NS) and fewer
-    // than PD tiles are in flight; the oldest tile in flight is published
-    // (its slot's sequence number set) once its loads have landed.
-    uint32_t seq0 = 0;                                // first tile of the item
+    // Slot load seq (TPS tiles, their mask words and FP8 scales) goes to
+    // slot seq % NS.  It is issued once every compute wavefront is done with
+    // the slot's previous load (seq - NS) and fewer than PD loads are in
+    // flight; the oldest load in flight is published (the slot's sequence
+    // number set) once its data have landed.  Every slot load is the same
+    // R::LS instructions, so the memory counter tells which have landed.
+    uint32_t seq0 = 0;                                // first slot load of the item
     for (;;) {
       wg_barrier();
       const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform
@@ -1145,47 +1158,36 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       if (item >= my_items) break;
       uint64_t g0, g1;
       item_range(item, g0, g1);
-      const uint32_t n_t = (uint32_t)(g1 - g0) * (kGroup / kTile);
-      const uint64_t tile0 = g0 * (uint64_t)(kGroup / kTile);
+      const uint32_t n_s = (uint32_t)(g1 - g0) * SPG;
       const uint32_t qt = item % n_qtiles;
-      // mask words of group g (item-relative gi) into buffer (seq of its
-      // first tile / 32) % 2: the first group's before its first tile, the
-      // others word by word with the second half of the previous group's
-      // tiles (by then every compute wavefront has left the group that used
-      // the buffer before); other tiles carry padding loads, so that every
-      // tile is LT loads
-      auto dma_mask = [&](uint32_t gi, int w) {
-        const uint32_t buf = ((seq0 >> 5) + gi) & 1u;
-        const uint64_t* src = a.mw + ((g0 + gi) * kWords + (uint64_t)w) * a.ppad +
-                              (uint64_t)qt * QT + 2u * lane;
+      // slot load c: tiles c*TPS .. of the item, mask words (c*TPS)/2 ..
+      auto dma_slot = [&](uint32_t c, uint8_t* sp) {
+        const uint64_t tile = g0 * (uint64_t)(kGroup / kTile) + (uint64_t)c * TPS;
 #pragma unroll
-        for (int k = 0; k < LM; ++k)
-          __builtin_amdgcn_global_load_lds((const void*)(src + 128 * k),
-                                           (__attribute__((address_space(3))) void*)
-                                               ((uint8_t*)&s_mask[buf][w][0] + 1024 * k),
-                                           16, 0, 0);
-      };
-      // (padding loads of different workgroups read different kilobytes of
-      // the mask buffer, which holds at least 16 x 256 words, so that no
-      // single line is read by every CU at every tile)
-      const uint64_t* pad_src = a.mw + (uint64_t)(blockIdx.x % 32u) * 128u + 2u * lane;
-      auto dma_pad = [&]() {
+        for (int u = 0; u < TPS; ++u)
+          dma_tile<DT, CH>(a.tiles, a.xscale, tile + u, sp + u * R::TB,
+                           (float*)(sp + R::SOFF) + u * kTile, lane);
+        const uint64_t g = g0 + (c * TPS) / (kGroup / kTile);
+        const uint32_t w0 = ((c * TPS) % (kGroup / kTile)) / 2;
 #pragma unroll
-        for (int k = 0; k < LM; ++k)
-          __builtin_amdgcn_global_load_lds((const void*)pad_src,
-                                           (__attribute__((address_space(3))) void*)
-                                               (s_msink + 1024 * k),
-                                           16, 0, 0);
+        for (int wl = 0; wl < R::WPC; ++wl) {
+          const uint64_t* src = a.mw + (g * kWords + w0 + wl) * a.ppad + (uint64_t)qt * QT + 2u * lane;
+#pragma unroll
+          for (int k = 0; k < R::LM; ++k)
+            __builtin_amdgcn_global_load_lds(
+                (const void*)(src + 128 * k),
+                (__attribute__((address_space(3))) void*)(sp + R::MOFF + wl * QT * 8 + 1024 * k),
+                16, 0, 0);
+        }
       };
-      for (int w = 0; w < kWords; ++w) dma_mask(0u, w);
       wg_barrier();                                   // set-up
       uint32_t issued = 0, published = 0;
       // least done-counter over the compute wavefronts as last read: the
       // counters only grow, so a slot it shows free is free
       uint32_t mind = 0;
-      while (published < n_t) {
+      while (published < n_s) {
         bool moved = false;
-        while (issued < n_t && issued - published < (uint32_t)PD) {
+        while (issued < n_s && issued - published < (uint32_t)PD) {
           const uint32_t sq = seq0 + issued;
           if (sq >= (uint32_t)NS && mind < sq - (uint32_t)NS + 1u) {
             uint32_t m = 0xFFFFFFFFu;
@@ -1197,17 +1199,12 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
             mind = __builtin_amdgcn_readfirstlane(m);
             if (mind < sq - (uint32_t)NS + 1u) break;   // slot still in use
           }
-          const uint32_t slot = sq % (uint32_t)NS;
-          const uint32_t gi = issued >> 5, t = issued & 31u;
-          if (t >= 16u && gi + 1u < n_t / 32u) dma_mask(gi + 1u, (int)(t - 16u));
-          else dma_pad();
-          dma_tile<DT, CH>(a.tiles, a.xscale, tile0 + issued, s_ring + slot * R::TB,
-                           s_rscale + slot * kTile, lane);
+          dma_slot(issued, s_ring + (sq % (uint32_t)NS) * R::SB);
           ++issued;
           moved = true;
         }
         if (published < issued) {
-          wait_tiles<LT, PD>(issued - published - 1u);
+          wait_slots<R::LS, PD>(issued - published - 1u);
           const uint32_t sq = seq0 + published;
           if (lane == 0) lds_word_st(&s_ready[sq % (uint32_t)NS], sq);
           ++published;
@@ -1215,7 +1212,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
         }
         if (!moved) __builtin_amdgcn_s_sleep(1);
       }
-      seq0 += n_t;
+      seq0 += n_s;
       wg_barrier();                                   // item end
     }
     return;
@@ -1461,7 +1458,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       s_stail[i] = 0u;
     }
   }
-  uint32_t seq0 = 0;            // sequence number of the item's first tile
+  uint32_t seq0 = 0;            // sequence number of the item's first slot load
   uint32_t item_no = 0;
   uint32_t shead = 0;           // this wavefront's staging head (it is the only writer)
 
@@ -1475,10 +1472,6 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     return qt * QT + (uint32_t)((bw * QB + b) * 32 + col);
   };
   auto my_j = [&](int b) -> int { return (bw * QB + b) * 32 + col; };
-  // mask word w of this lane's query in block b, group buffer mb
-  auto smask = [&](int mb, int b, int w) -> uint64_t {
-    return s_mask[mb][w][(bw * QB + b) * 32 + col];
-  };
   auto load_queries = [&](uint32_t qt) {
     const uint32_t valid = min((uint32_t)QT, n_list - qt * (uint32_t)QT);
     const uint32_t nb = (valid + 32u * QB - 1u) / (32u * QB);
@@ -1538,50 +1531,57 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     }
     wg_barrier();                                     // set-up
 
-    for (uint64_t g = g0; g < g1; ++g) {
-      const uint32_t ti0 = (uint32_t)(g - g0) * (kGroup / kTile);   // item-relative tile
-      // the group's masks have landed once its first tile is published
-      const uint32_t sq0 = seq0 + ti0;
-      while (lds_get(&s_ready[sq0 % (uint32_t)NS]) != sq0) __builtin_amdgcn_s_sleep(1);
-      const int mb = (int)((sq0 >> 5) & 1u);
-      // tiles of this group that some query of this wavefront matches
-      uint32_t act = 0;
+    const uint32_t n_s = (uint32_t)(g1 - g0) * SPG;
 #pragma unroll 1
-      for (int w = 0; w < kWords; ++w) {
+    for (uint32_t c = 0; c < n_s; ++c) {
+      // one step per ring slot: wait until the loader has published it,
+      // then score each of its tiles that a query of this wavefront matches
+      const uint32_t sq = seq0 + c;
+      const uint32_t rs = sq % (uint32_t)NS;
+      while (lds_get(&s_ready[rs]) != sq) __builtin_amdgcn_s_sleep(1);
+      const uint8_t* sp = s_ring + rs * R::SB;
+      const uint64_t* smw = (const uint64_t*)(sp + R::MOFF);   // [word][QT]
+      const uint32_t tg0 = (c * TPS) % (kGroup / kTile);      // first tile, within its group
+      const uint64_t tile0 = g0 * (uint64_t)(kGroup / kTile) + (uint64_t)c * TPS;
+      // bit u: tile u of the slot has a match for some query of this wavefront
+      uint32_t act = 0;
+#pragma unroll
+      for (int wl = 0; wl < R::WPC; ++wl) {
         uint64_t o = 0;
 #pragma unroll
         for (int b = 0; b < QB; ++b)
-          if (kp[b]) o |= smask(mb, b, w);
-        if (__ballot((uint32_t)o != 0u)) act |= 1u << (2 * w);
-        if (__ballot((uint32_t)(o >> 32) != 0u)) act |= 2u << (2 * w);
-      }
-
-      const uint64_t tile0 = g * (uint64_t)(kGroup / kTile);
-      // one step per tile of the group: wait for the tile's ring slot, then
-      // (if a query of this wavefront matches the tile) score it
-      auto body = [&](int t) {
-        const uint32_t sq = seq0 + ti0 + (uint32_t)t;
-        const uint32_t rs = sq % (uint32_t)NS;
-        // wait until the loader has published the tile
-        while (lds_get(&s_ready[rs]) != sq) __builtin_amdgcn_s_sleep(1);
-        if (!((act >> t) & 1u) || (uint32_t)t % tstride != tslot) {
-          lds_put(&s_done[wave], sq + 1u);
-          return;
+          if (kp[b]) o |= smw[wl * QT + my_j(b)];
+        if constexpr (TPS == 1) {
+          if (__ballot((uint32_t)(o >> ((tg0 & 1u) * 32u)) != 0u)) act = 1u;
+        } else {
+          if (__ballot((uint32_t)o != 0u)) act |= 1u << (2 * wl);
+          if (__ballot((uint32_t)(o >> 32) != 0u)) act |= 2u << (2 * wl);
         }
+      }
+      if (act) {
 #pragma unroll
         for (int b = 0; b < QB; ++b) thr[b] = s_thr[my_j(b)];
+      }
+      // the staging ring's tail as of now (it only advances, so the room
+      // computed from it is a lower bound)
+      const uint32_t tail0 = __atomic_load_n(&s_stail[wave], __ATOMIC_RELAXED);
+#pragma unroll
+      for (int u = 0; u < TPS; ++u) {
+        const uint32_t t = tg0 + (uint32_t)u;                 // tile within its group
+        const int wl = TPS == 1 ? 0 : u / 2;                  // its mask word in the slot
+        if (!((act >> u) & 1u) || t % tstride != tslot) continue;
         f32x16 accs[QB];
 #pragma unroll
         for (int b = 0; b < QB; ++b)
 #pragma unroll
           for (int v = 0; v < 16; ++v) accs[b][v] = 0.f;
-        mma_tile<DT, CH, QB>(accs, s_ring + rs * R::TB, bq, lane);
+        mma_tile<DT, CH, QB>(accs, sp + u * R::TB, bq, lane);
         float4 xs[4];
-        if constexpr (DT == kFP8) read_scales(xs, s_rscale + rs * kTile, lane);
+        if constexpr (DT == kFP8) read_scales(xs, (const float*)(sp + R::SOFF) + u * kTile, lane);
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
           f32x16& acc = accs[b];
-          const uint32_t m32 = (uint32_t)(smask(mb, b, t >> 1) >> ((t & 1) * 32));
+          const uint32_t m32 = (uint32_t)(smw[wl * QT + my_j(b)] >> ((t & 1u) * 32u));
           if constexpr (DT == kFP8) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
@@ -1590,38 +1590,35 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
               acc[v] = (acc[v] * qs[b]) * sc;
             }
           }
-          const f32x16& s = acc;
-          // largest score among the lane's rows that satisfy the predicate:
-          // a row's mask bit, sign-extended, selects its score or -inf, so
-          // the candidate step below runs only when a matching row reaches
-          // the threshold
+          // rows that fail the predicate become -inf: a row's mask bit
+          // (row 8g + 4 half + i = acc_row(4g + i, half) is bit 8g + i of
+          // the lane's shifted word), sign-extended, selects its score or
+          // -inf.  The threshold is at least -FLT_MAX, so a row passes it
+          // only if it matches and scores at least the threshold, and the
+          // candidate step runs only when some row of the wavefront does.
           const uint32_t mrow = m32 >> (4 * half);
           float mx = -INFINITY;
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const uint32_t sel = (uint32_t)__builtin_amdgcn_sbfe(
                 (int)mrow, 8 * (v >> 2) + (v & 3), 1);
-            const uint32_t bits = (__float_as_uint(s[v]) & sel) | (0xFF800000u & ~sel);
-            mx = fmaxf(mx, __uint_as_float(bits));
+            acc[v] = __uint_as_float((__float_as_uint(acc[v]) & sel) | (0xFF800000u & ~sel));
+            mx = fmaxf(mx, acc[v]);
           }
-          const bool cand = (m32 != 0u) && (mx >= thr[b]);
-          if (__ballot(cand)) {
-            // mask bits of the lane's 16 accumulator rows: row 8g + 4 half + i
-            // (= acc_row(4g + i, half)) goes to bit 4g + i
-            const uint32_t mh = cand ? m32 >> (4 * half) : 0u;
-            const uint32_t msel = (mh & 0xFu) | ((mh >> 4) & 0xF0u) | ((mh >> 8) & 0xF00u) |
-                                  ((mh >> 12) & 0xF000u);
+          const f32x16& s = acc;
+          const float th = fmaxf(thr[b], -FLT_MAX);
+          if (__ballot(mx >= th)) {
             {
               // wave-wide compaction: the v-th survivors of all lanes take
               // consecutive staging slots (this wavefront is the only writer
               // of its buffer, so the count needs no atomic)
               const uint32_t q = qi[b];
               const int jj = my_j(b);
-              const uint32_t room = (uint32_t)SR - (shead - lds_get(&s_stail[wave]));
+              const uint32_t room = (uint32_t)SR - (shead - tail0);
               uint32_t base = 0;
 #pragma unroll
               for (int v = 0; v < 16; ++v) {
-                const bool on = ((msel >> v) & 1u) && s[v] >= thr[b];
+                const bool on = s[v] >= th;
                 const uint64_t bal = __ballot(on);
                 if (bal == 0ull) continue;
                 const uint32_t idx = base + __builtin_amdgcn_mbcnt_hi(
@@ -1629,7 +1626,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                 base += (uint32_t)__popcll(bal);
                 if (on) {
-                  const uint64_t slot = (tile0 + t) * kTile + acc_row(v, half);
+                  const uint64_t slot = (tile0 + u) * kTile + acc_row(v, half);
                   const uint32_t k32 = fkey(s[v]);
                   // the id (for the tie order) is looked up by the selection
                   const unsigned long long key =
@@ -1655,16 +1652,13 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
             }
           }
         }
-        if (lane == 0) {
-          lds_put(&s_shead[wave], shead);
-          lds_put(&s_done[wave], sq + 1u);
-        }
-      };
-
-#pragma unroll 1
-      for (int t = 0; t < kGroup / kTile; ++t) body(t);
+      }
+      if (lane == 0) {
+        lds_put(&s_shead[wave], shead);
+        lds_put(&s_done[wave], sq + 1u);
+      }
     }
-    seq0 += (uint32_t)(g1 - g0) * (kGroup / kTile);
+    seq0 += n_s;
     if (lane == 0) lds_put(&s_fin[wave], item_no);
     ++item_no;
     wg_barrier();                                     // item end
@@ -1711,7 +1705,7 @@ hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int 
     FR_REQUIRE(a.qscale);
   }
   if (a.gpi < 1 || n_wg < 1) return hipErrorInvalidValue;
-  // the loader's padding loads read the first 4096 words of the masks
+  // the loader copies whole query tiles (128 or 256 positions) of mask words
   if (a.ppad < 256u || a.ppad % 256u) return hipErrorInvalidValue;
 #define FR_LAUNCH(D, P, Q, W)                                                          \
   if (dt == D && dpad == P && qb == Q && nw == W) {                                    \

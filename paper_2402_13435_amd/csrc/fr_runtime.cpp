@@ -250,8 +250,7 @@ size_t layout_workspace(const fr_index* ix, Workspace& w, uint8_t* base, uint32_
   carve(&w.cand_key, base, off, (size_t)qm * cand_cap);
   carve(&w.skey, base, off, (size_t)qm * seed_row(ix));
   carve(&w.tsafe, base, off, qm);
-  // the scan's padding loads read the first 4096 words of the masks
-  carve(&w.mw, base, off, std::max<size_t>((size_t)n_groups * kWords * w.ppad, 4096));
+  carve(&w.mw, base, off, (size_t)std::max<uint64_t>(n_groups, 1) * kWords * w.ppad);
   carve(&w.sel_key, base, off, (size_t)qm * ix->rmax);
   carve(&w.sel_slot, base, off, (size_t)qm * ix->rmax);
   if (outputs) {
