@@ -118,29 +118,6 @@ struct PrepArgs {
   uint32_t* linfo;
 };
 
-// Second pass for the queries the first one could not answer: those whose
-// candidate buffer overflowed keep their (safe, tightened) threshold with
-// the histogram range narrowed to [tau, max seen]; those whose speculative
-// starting threshold proved too high restart from the safe one.  Their
-// counters are cleared.
-struct RerunArgs {
-  uint32_t max_q;
-  const uint32_t* n_dev;
-  uint32_t* ovf;           // 1: overflow, 2: speculative start too high
-  uint32_t* qlist2;
-  uint32_t* n_list2;
-  const uint32_t* kp;
-  uint32_t* tau;
-  uint32_t* tsafe;
-  const float* qnorm;
-  const uint32_t* norm_max;
-  uint32_t* cnt;
-  uint32_t* smax;
-  uint32_t* hist;
-  float* hlo;
-  float* hinvw;
-  uint32_t* work;
-};
 
 // Predicate masks of one search pass, precomputed for the scan: word w of
 // group g for the query at position p of the pass's list is
@@ -220,14 +197,29 @@ struct ScanArgs {
   uint32_t ppad;
 };
 
+// Exact selection of a pass's candidates.  The first pass also sets up the
+// second one for the queries it cannot answer: those whose candidate buffer
+// overflowed keep their (safe, tightened) threshold with the histogram range
+// narrowed to [tau, max seen]; those whose speculative starting threshold
+// proved too high restart from the safe one.  Their counters are cleared and
+// they are appended to qlist2.
 struct SelectArgs {
   const uint32_t* qlist;
   const uint32_t* n_list;  // device
   uint32_t max_list;       // grid size
   int final_pass;          // overflow here is final: mark the query failed
   const uint32_t* kp;
-  const uint32_t* tau;
-  const uint32_t* cnt;
+  uint32_t* tau;
+  uint32_t* cnt;
+  uint32_t* smax;
+  uint32_t* hist;
+  float* hlo;
+  float* hinvw;
+  uint32_t* qlist2;        // second pass list (first pass appends)
+  uint32_t* n_list2;
+  uint32_t* work;          // work counters, zeroed for the second scan
+  const float* qnorm;
+  const uint32_t* norm_max;
   const unsigned long long* cand_key;   // score key << 32 | slot
   const uint32_t* slot_ids;            // slot -> external id
   uint32_t cap;
@@ -235,8 +227,8 @@ struct SelectArgs {
   uint32_t* sel_slot;
   uint32_t* sel_cnt;
   uint32_t rmax;
-  uint32_t* ovf;
-  const uint32_t* tsafe;   // first pass: nonzero where the start was speculative
+  uint32_t* ovf;           // final pass: 1 where the query failed
+  uint32_t* tsafe;         // first pass: nonzero where the start was speculative
   // direct output (FP32 path)
   int write_out;
   const uint32_t* k;
@@ -274,7 +266,9 @@ hipError_t launch_tile_rows(const TileRowsArgs& a, hipStream_t s);
 hipError_t launch_terms(const TermArgs& a, hipStream_t s);
 hipError_t launch_live(const LiveArgs& a, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
-hipError_t launch_rerun(const RerunArgs& a, hipStream_t s);
+// Query tiling (t, over the batch's rows) fused with the per-query state of
+// launch_prep (a); t.n == a.max_q and t.n_dev == a.n_dev.
+hipError_t launch_query_prep(const TileRowsArgs& t, const PrepArgs& a, hipStream_t s);
 hipError_t launch_mask_words(const MaskWordArgs& a, hipStream_t s);
 hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s);
 hipError_t launch_zero_work(uint32_t* work, hipStream_t s);

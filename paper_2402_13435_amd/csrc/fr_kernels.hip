@@ -157,15 +157,11 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {
 // ------------------------------------------------------------- tile rows
 // One wavefront per row: FP32 row -> tiled storage in the index dtype
 // (+ FP8 row scale, optional FP32 master copy, row norm).
+// Returns the row's L2 norm (in every lane).
 template <int DT>
-__global__ __launch_bounds__(256) void k_tile_rows(TileRowsArgs a) {
+__device__ __forceinline__ float tile_row(const TileRowsArgs& a, uint64_t row, int lane) {
   constexpr int ES = DT == kF32 ? 4 : DT == kBF16 ? 2 : 1;
   constexpr int PC = 16 / ES;  // elements per 16-byte chunk
-  const int lane = threadIdx.x & 63;
-  const uint64_t row = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  uint64_t n = a.n;
-  if (a.n_dev) n = min(n, (uint64_t)*a.n_dev);
-  if (row >= n) return;
   const uint64_t slot = a.slots ? (uint64_t)a.slots[row] : a.slot_base + row;
   const int dpad = (int)a.dpad, dim = (int)a.dim, hd = dpad / 2;
   float x[4];
@@ -182,8 +178,8 @@ __global__ __launch_bounds__(256) void k_tile_rows(TileRowsArgs a) {
     ss += __shfl_xor(ss, off);
     amax = fmaxf(amax, __shfl_xor(amax, off));
   }
+  const float nrm = sqrtf(ss);
   if (lane == 0) {
-    const float nrm = sqrtf(ss);
     if (a.norm) a.norm[row] = nrm;
     if (a.norm_max) atomicMax(a.norm_max, __float_as_uint(nrm));
   }
@@ -210,6 +206,17 @@ __global__ __launch_bounds__(256) void k_tile_rows(TileRowsArgs a) {
       *dst = to_e4m3_rne(x[i] * inv);
     }
   }
+  return nrm;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_tile_rows(TileRowsArgs a) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t row = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  uint64_t n = a.n;
+  if (a.n_dev) n = min(n, (uint64_t)*a.n_dev);
+  if (row >= n) return;
+  (void)tile_row<DT>(a, row, lane);
 }
 
 hipError_t launch_tile_rows(const TileRowsArgs& a, hipStream_t s) {
@@ -316,16 +323,16 @@ hipError_t launch_check_finite(const float* x, uint64_t n, uint32_t* flag, hipSt
 // ------------------------------------------------------------- prep
 // One wavefront per query: the lanes clear its histogram, lane 0 sets the
 // per-query state and builds the literal table.
-__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t q = blockIdx.x * 4u + (threadIdx.x >> 6);
-  const uint32_t n_q = *a.n_dev;
+__device__ __forceinline__ void prep_block0(const PrepArgs& a, uint32_t n_q) {
   if (blockIdx.x == 0 && threadIdx.x < kXcds) a.work[threadIdx.x] = 0u;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *a.n_list = n_q;
     *a.n_list2 = 0u;
   }
-  if (q >= n_q || q >= a.max_q) return;
+}
+
+// Per-query state of query q (one wavefront), given its norm.
+__device__ __forceinline__ void prep_query(const PrepArgs& a, uint32_t q, int lane, float qn) {
   uint32_t* h = a.hist + (uint64_t)q * kHist;
   for (int i = lane; i < kHist; i += 64) h[i] = 0u;
   if (lane != 0) return;
@@ -348,7 +355,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   // negative scores get buckets too; the starting-threshold kernel narrows
   // it to [starting threshold, hi] when it finds one
   const float m = __uint_as_float(*a.norm_max);
-  const float hi = a.qnorm[q] * m * 1.0001f;
+  const float hi = qn * m * 1.0001f;
   const bool rng_ok = hi > 0.f && isfinite(hi);
   a.hlo[q] = rng_ok ? -hi : 0.f;
   a.hinvw[q] = rng_ok ? (float)kNBF / (2.f * hi) : 0.f;
@@ -374,6 +381,29 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   a.linfo[q] = (nl > L ? L : nl) | (starts << 8) | (empty << 24) | ((nl > L ? 1u : 0u) << 25) |
                ((c1 > c0 ? 1u : 0u) << 26);
 }
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t q = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint32_t n_q = *a.n_dev;
+  prep_block0(a, n_q);
+  if (q >= n_q || q >= a.max_q) return;
+  prep_query(a, q, lane, a.qnorm[q]);
+}
+
+// The batch's query rows into the query tiles (norms, FP8 scales, the FP32
+// copy the rescoring reads) and each query's per-search state, one
+// wavefront per query.
+template <int DT>
+__global__ __launch_bounds__(256) void k_query_prep(TileRowsArgs t, PrepArgs a) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t q = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint32_t n_q = *a.n_dev;
+  prep_block0(a, n_q);
+  if (q >= n_q || q >= a.max_q || q >= t.n) return;
+  const float qn = tile_row<DT>(t, q, lane);
+  prep_query(a, q, lane, qn);
+}
+
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
   FR_REQUIRE(a.n_dev);
   FR_REQUIRE(a.k);
@@ -402,82 +432,44 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_rerun(RerunArgs a) {
-  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x < kXcds) a.work[threadIdx.x] = 0u;
-  const uint32_t n_q = *a.n_dev;
-  if (q >= n_q || q >= a.max_q || !a.ovf[q]) return;
-  const uint32_t why = a.ovf[q];
-  a.ovf[q] = 0u;
-  const uint32_t p = atomicAdd(a.n_list2, 1u);
-  a.qlist2[p] = q;
-  uint32_t* h = a.hist + (uint64_t)q * kHist;
-  float lo, hi;
-  if (why == 2u) {
-    // The speculative start was above the K'-th best score: every match at
-    // or above it was seen (the largest is smax), the rest lie below it.
-    // Scan again from the safe start.
-    hi = fmaxf(key2f(a.smax[q]), key2f(a.tau[q]));
-    a.tau[q] = a.tsafe[q];
-    lo = key2f(a.tsafe[q]);
-    if (!isfinite(lo)) lo = -(a.qnorm[q] * __uint_as_float(*a.norm_max) * 1.0001f);
-  } else {
-    // Raise the threshold from the complete first-pass histogram: the scan's
-    // own refreshes may have seen only part of it.  Same bucket rule (and
-    // one-bucket margin) as the scan's refresh.
-    const uint32_t kp = a.kp[q];
-    const float lo0 = a.hlo[q], iw0 = a.hinvw[q];
-    uint32_t suffix = 0;
-    int bstar = -1;
-    for (int c = kNBC - 1; c >= 0 && bstar < 0; --c) {
-      if (suffix + h[c] < kp) {
-        suffix += h[c];
-        continue;
-      }
-      for (int f = 15; f >= 0; --f) {
-        suffix += h[kNBC + c * 16 + f];
-        if (suffix >= kp) {
-          bstar = c * 16 + f;
-          break;
-        }
-      }
-      if (bstar < 0) bstar = c * 16;   // coarse and fine counts disagree: stay safe
-    }
-    if (kp && bstar >= 2 && iw0 > 0.f) {
-      const uint32_t nk = fkey(lo0 + (float)(bstar - 1) / iw0);
-      if (nk > a.tau[q]) a.tau[q] = nk;
-    }
-    lo = key2f(a.tau[q]);
-    hi = key2f(a.smax[q]);
-  }
-  a.tsafe[q] = 0u;
-  const float span = (hi - lo) * 1.0001f;
-  const bool ok = span > 0.f && isfinite(span) && isfinite(lo);
-  a.hlo[q] = ok ? lo : 0.f;
-  a.hinvw[q] = ok ? (float)kNBF / span : 0.f;
-  a.cnt[q] = 0u;
-  a.smax[q] = 0u;
-  for (int i = 0; i < kHist; ++i) h[i] = 0u;
-}
-hipError_t launch_rerun(const RerunArgs& a, hipStream_t s) {
+hipError_t launch_query_prep(const TileRowsArgs& t, const PrepArgs& a, hipStream_t s) {
   FR_REQUIRE(a.n_dev);
-  FR_REQUIRE(a.ovf);
-  FR_REQUIRE(a.qlist2);
-  FR_REQUIRE(a.n_list2);
+  FR_REQUIRE(a.k);
   FR_REQUIRE(a.kp);
-  FR_REQUIRE(a.tau);
-  FR_REQUIRE(a.tsafe);
   FR_REQUIRE(a.qnorm);
   FR_REQUIRE(a.norm_max);
+  FR_REQUIRE(a.tau);
+  FR_REQUIRE(a.tsafe);
   FR_REQUIRE(a.cnt);
   FR_REQUIRE(a.smax);
   FR_REQUIRE(a.hist);
   FR_REQUIRE(a.hlo);
   FR_REQUIRE(a.hinvw);
+  FR_REQUIRE(a.nmatch);
+  FR_REQUIRE(a.qlist);
+  FR_REQUIRE(a.n_list);
+  FR_REQUIRE(a.n_list2);
   FR_REQUIRE(a.work);
-  hipLaunchKernelGGL(k_rerun, dim3(grid_for(a.max_q ? a.max_q : 1, 256)), dim3(256), 0, s, a);
+  FR_REQUIRE(a.ovf);
+  FR_REQUIRE(a.clause_off);
+  FR_REQUIRE(a.literal_off);
+  FR_REQUIRE(a.terms);
+  FR_REQUIRE(a.lit);
+  FR_REQUIRE(a.linfo);
+    FR_REQUIRE(t.rows);
+  FR_REQUIRE(t.tiles);
+  if (t.dt == kFP8) FR_REQUIRE(t.scale);
+  if (t.dpad % 64 || t.dpad > 256 || t.dim > t.dpad || t.n_dev != a.n_dev || t.n != a.max_q)
+    return hipErrorInvalidValue;
+  const dim3 g(grid_for(a.max_q ? a.max_q : 1, 4)), b(256);
+  switch (t.dt) {
+    case kF32: hipLaunchKernelGGL(k_query_prep<kF32>, g, b, 0, s, t, a); break;
+    case kBF16: hipLaunchKernelGGL(k_query_prep<kBF16>, g, b, 0, s, t, a); break;
+    default: hipLaunchKernelGGL(k_query_prep<kFP8>, g, b, 0, s, t, a); break;
+  }
   return hipGetLastError();
 }
+
 
 // Predicate masks of a search pass (Sec. 5.3: a document passes when every
 // clause of the query's CNF has a term the document carries; with the live
@@ -1749,6 +1741,66 @@ __device__ __forceinline__ int pow2_at_least(int n) {
   return p;
 }
 
+// First pass only: the query could not be answered from this pass (why 1:
+// its candidates overflowed the buffer; why 2: its speculative starting
+// threshold proved above the K'-th best).  Set it up for the second pass
+// and append it to that pass's list.  Called by the whole workgroup.
+__device__ void select_rerun(const SelectArgs& a, uint32_t q, uint32_t why) {
+  uint32_t* h = a.hist + (uint64_t)q * kHist;
+  if (threadIdx.x == 0) {
+    float lo, hi;
+    if (why == 2u) {
+      // every match at or above the speculative start was seen (the
+      // largest is smax), the rest lie below it: scan again from the safe
+      // start
+      hi = fmaxf(key2f(a.smax[q]), key2f(a.tau[q]));
+      a.tau[q] = a.tsafe[q];
+      lo = key2f(a.tsafe[q]);
+      if (!isfinite(lo)) lo = -(a.qnorm[q] * __uint_as_float(*a.norm_max) * 1.0001f);
+    } else {
+      // raise the threshold from the complete first-pass histogram (the
+      // scan's own refreshes may have seen only part of it): same bucket
+      // rule and one-bucket margin as the scan's refresh
+      const uint32_t kp = a.kp[q];
+      const float lo0 = a.hlo[q], iw0 = a.hinvw[q];
+      uint32_t suffix = 0;
+      int bstar = -1;
+      for (int c = kNBC - 1; c >= 0 && bstar < 0; --c) {
+        if (suffix + h[c] < kp) {
+          suffix += h[c];
+          continue;
+        }
+        for (int f = 15; f >= 0; --f) {
+          suffix += h[kNBC + c * 16 + f];
+          if (suffix >= kp) {
+            bstar = c * 16 + f;
+            break;
+          }
+        }
+        if (bstar < 0) bstar = c * 16;   // coarse and fine counts disagree: stay safe
+      }
+      if (kp && bstar >= 2 && iw0 > 0.f) {
+        const uint32_t nk = fkey(lo0 + (float)(bstar - 1) / iw0);
+        if (nk > a.tau[q]) a.tau[q] = nk;
+      }
+      lo = key2f(a.tau[q]);
+      hi = key2f(a.smax[q]);
+    }
+    a.tsafe[q] = 0u;
+    const float span = (hi - lo) * 1.0001f;
+    const bool ok = span > 0.f && isfinite(span) && isfinite(lo);
+    a.hlo[q] = ok ? lo : 0.f;
+    a.hinvw[q] = ok ? (float)kNBF / span : 0.f;
+    a.cnt[q] = 0u;
+    a.smax[q] = 0u;
+    a.sel_cnt[q] = 0u;
+    const uint32_t p = atomicAdd(a.n_list2, 1u);
+    a.qlist2[p] = q;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHist; i += blockDim.x) h[i] = 0u;
+}
+
 // Exact top-kp of one query's candidates (those at or above the final
 // threshold), sorted by key descending = (score desc, id asc).
 __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
@@ -1757,18 +1809,24 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
   __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_n, s_digit, s_rank;
   const uint32_t pos = blockIdx.x;
+  // the first pass's scan is over: its work counters serve the second one
+  if (!a.final_pass && blockIdx.x == 0 && threadIdx.x < kXcds) a.work[threadIdx.x] = 0u;
   if (pos >= *a.n_list) return;
   const uint32_t q = a.qlist[pos];
   const uint32_t kp = a.kp[q];
   const uint32_t c = a.cnt[q];
   if (c > a.cap) {
-    // Candidates were dropped: leave the query for a second pass, or, if
-    // this was it, mark it failed (count 0xFFFFFFFF, no ids).
+    // Candidates were dropped: scan the query again, or, if this was the
+    // second pass, mark it failed (count 0xFFFFFFFF, no ids).
+    if (!a.final_pass) {
+      select_rerun(a, q, 1u);
+      return;
+    }
     if (threadIdx.x == 0) {
       a.ovf[q] = 1u;
       a.sel_cnt[q] = 0u;
     }
-    if (a.write_out && a.final_pass) {
+    if (a.write_out) {
       for (uint32_t r = threadIdx.x; r < a.k_max; r += blockDim.x) {
         a.out_ids[(uint64_t)q * a.k_max + r] = 0xFFFFFFFFu;
         a.out_scores[(uint64_t)q * a.k_max + r] = -INFINITY;
@@ -1784,10 +1842,7 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     // The speculative starting threshold was above the K'-th best match
     // (fewer candidates than min(K', matches) reached it): scan again from
     // the safe one.
-    if (threadIdx.x == 0) {
-      a.ovf[q] = 2u;
-      a.sel_cnt[q] = 0u;
-    }
+    select_rerun(a, q, 2u);
     return;
   }
   const uint32_t tau = a.tau[q];
@@ -1901,6 +1956,15 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
   FR_REQUIRE(a.ovf);
   FR_REQUIRE(a.tsafe);
   FR_REQUIRE(a.nmatch);
+  FR_REQUIRE(a.hist);
+  FR_REQUIRE(a.smax);
+  FR_REQUIRE(a.hlo);
+  FR_REQUIRE(a.hinvw);
+  FR_REQUIRE(a.qlist2);
+  FR_REQUIRE(a.n_list2);
+  FR_REQUIRE(a.work);
+  FR_REQUIRE(a.qnorm);
+  FR_REQUIRE(a.norm_max);
   if (a.rmax > (uint32_t)kMaxR || a.rmax < 1) return hipErrorInvalidValue;
   if (a.write_out) {
     FR_REQUIRE(a.k);

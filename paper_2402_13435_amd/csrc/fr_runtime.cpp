@@ -417,7 +417,7 @@ void pick_tiling(const fr_index* ix, uint32_t n_q, int* qb, int* nw) {
 int pick_gpi(const fr_index* ix, uint32_t n_q, int qt, uint32_t n_groups) {
   if (ix->gpi) return ix->gpi;
   const uint64_t qtiles = (n_q + qt - 1) / qt;
-  const uint64_t g = (uint64_t)n_groups * qtiles / (2ull * ix->n_wg);
+  const uint64_t g = ((uint64_t)n_groups * qtiles + ix->n_wg) / (2ull * ix->n_wg);
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 16));
 }
 
@@ -497,9 +497,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   ta.tiles = w.qtiles;
   ta.scale = w.qscale;
   ta.norm = w.qnorm;
-  FR_HIP(launch_tile_rows(ta, s));
-
-  FR_HIP(launch_prep(prep_args(ix, w), s));
+  FR_HIP(launch_query_prep(ta, prep_args(ix, w), s));
   const MaskWordArgs ma = mask_args(ix, w, n_groups);
   FR_HIP(launch_mask_words(ma, s));
 
@@ -563,6 +561,15 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   se.kp = w.kp;
   se.tau = w.tau;
   se.cnt = w.cnt;
+  se.smax = w.smax;
+  se.hist = w.hist;
+  se.hlo = w.hlo;
+  se.hinvw = w.hinvw;
+  se.qlist2 = w.qlist2;
+  se.n_list2 = w.desc + 2;
+  se.work = w.work;
+  se.qnorm = w.qnorm;
+  se.norm_max = ix->norm_max;
   se.cand_key = w.cand_key;
   se.slot_ids = ix->slot_ids;
   se.cap = w.cand_cap;
@@ -582,25 +589,8 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   se.out_nmatch = o_nmatch;
   FR_HIP(launch_select(se, s));
 
-  // second pass for overflowed queries (an empty list when none did)
-  RerunArgs ra{};
-  ra.max_q = w.qcap;
-  ra.n_dev = w.desc;
-  ra.ovf = w.ovf;
-  ra.qlist2 = w.qlist2;
-  ra.n_list2 = w.desc + 2;
-  ra.kp = w.kp;
-  ra.tau = w.tau;
-  ra.tsafe = w.tsafe;
-  ra.qnorm = w.qnorm;
-  ra.norm_max = ix->norm_max;
-  ra.cnt = w.cnt;
-  ra.smax = w.smax;
-  ra.hist = w.hist;
-  ra.hlo = w.hlo;
-  ra.hinvw = w.hinvw;
-  ra.work = w.work;
-  FR_HIP(launch_rerun(ra, s));
+  // second pass for the queries the first could not answer (an empty list
+  // when there are none)
   MaskWordArgs mb = ma;
   mb.qlist = w.qlist2;
   mb.n_list = w.desc + 2;

@@ -32,7 +32,7 @@ def assigned(var):
 
 def test_search_launch_args_fully_assigned():
     for struct, var in (("PrepArgs", "pa"), ("ScanArgs", "sa"), ("SelectArgs", "se"),
-                        ("RerunArgs", "ra"), ("RescoreArgs", "rs"),
+                        ("RescoreArgs", "rs"),
                         ("MaskWordArgs", "ma"), ("SeedArgs", "sd")):
         missing = set(struct_fields(struct)) - assigned(var)
         assert not missing, f"{struct} {var}: unassigned {sorted(missing)}"
@@ -41,7 +41,7 @@ def test_search_launch_args_fully_assigned():
 def test_launchers_guard_pointers():
     text = open(os.path.join(CSRC, "fr_kernels.hip")).read()
     for launcher, struct in (("launch_prep", "PrepArgs"), ("launch_scan", "ScanArgs"),
-                             ("launch_rerun", "RerunArgs"), ("launch_select", "SelectArgs"),
+                             ("launch_select", "SelectArgs"),
                              ("launch_rescore", "RescoreArgs"),
                              ("launch_mask_words", "MaskWordArgs"), ("launch_seed", "SeedArgs")):
         body = text[text.index("hipError_t %s(" % launcher):]
