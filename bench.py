@@ -144,10 +144,13 @@ def check_parity(o, qb, k: int, oracle_res: dict, ids, scores, counts, nmatch) -
 
 
 def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None, blocks=1,
-             host=True):
+             host=True, tune=None):
     """One index, warm-up searches, then `blocks` timed blocks of `steps`
     searches; the elapsed time reported is the median block's (the FP32
-    benchmark line uses one block)."""
+    benchmark line uses one block).  Without a pinned `tiling` the
+    autotuner picks the tiling and search strategy on the batch `tune` (a
+    disjoint batch of the same shape; `qb` itself if None) and later searches
+    use its choice through the index's tuning table."""
     from paper_2402_13435_amd import Index, SearchResult
     # two workspaces: the host prepares the next search while the device runs
     # the current one
@@ -157,7 +160,8 @@ def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None, bl
     if tiling:
         ix.set_tiling(*tiling)
     else:
-        tiling = ix.autotune(qb.emb, qb, k)
+        t = tune if tune is not None else qb
+        tiling = ix.autotune(t.emb, t, k)
     dev = torch.device("cuda:0")
     q = torch.from_numpy(qb.emb).to(dev)
     n_q = qb.n
@@ -195,6 +199,26 @@ def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None, bl
     ix.close()
     return {"elapsed": elapsed, "scan_ms": scan_ms, "total_ms": total_ms, "stats": stats,
             "res": res, "tiling": tiling, "host_qps": host_qps}
+
+
+def scan_roofline(c, dtype: str, n_q: int, stats, scan_ms: float) -> dict:
+    """The scan kernel against both roofs: its algorithmic bytes (each live
+    document's stored row once: dpad x element bytes, + 4 for the FP8 row
+    scale; one bit per document for each term the batch references; the live
+    bits) and its dense flops 2 d Q N, each per second against the HBM peak
+    and the matrix peak of its dtype; `bound` names the larger fraction."""
+    dpad = (c.cfg.dim + 63) // 64 * 64
+    per_doc = dpad * {"f32": 4, "bf16": 2, "fp8": 1}[dtype] + (4 if dtype == "fp8" else 0)
+    n = stats.n_live
+    alg_bytes = n * per_doc + n * stats.n_terms_batch / 8.0 + n / 8.0
+    flops = 2.0 * c.cfg.dim * n_q * n
+    t = scan_ms * 1e-3
+    gbs = alg_bytes / t / 1e9
+    tfs = flops / t / 1e12
+    f_hbm, f_mma = gbs / PEAKS["hbm_gbs"], tfs / PEAKS[dtype]
+    return {"bound": "hbm" if f_hbm >= f_mma else "mfma", "scan_ms": round(scan_ms, 4),
+            "alg_bytes": alg_bytes, "hbm_gbs": round(gbs, 1), "hbm_frac": round(f_hbm, 4),
+            "mfma_tflops": round(tfs, 2), "mfma_frac": round(f_mma, 4)}
 
 
 def stratified(qb, n: int):
@@ -257,48 +281,67 @@ def timed_search(torch, ix, qb, k, steps, warmup, graph=False):
             "count": out.count.cpu().numpy().view(np.uint32)}
 
 
-def bench_precision(args, torch):
+def precision_leg(args, torch, n_docs: int = 0):
     """10M x 256 corpus: BF16 and FP8 (first pass) + FP32 rescoring of R=4096
     candidates vs the plain FP32 path on the same data; recall@100 and max
-    score error against the FP64 oracle on a stratified query sample."""
+    score error against the FP64 oracle on a stratified query sample (the
+    oracle on a thread pool over the host cores).  Each form's tiling and
+    strategy are autotuned on a disjoint batch of the same shape."""
     import datagen
     from paper_2402_13435_amd import Index
     cfg = datagen.CONFIGS["precision"]
-    if args.n_docs:
-        cfg = datagen.scaled(cfg, args.n_docs)
+    if n_docs:
+        cfg = datagen.scaled(cfg, n_docs)
     log(f"generating the precision workload ({cfg.n_docs} docs x {cfg.dim})")
     c = datagen.corpus(cfg)
-    qb = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms))
+    df = datagen.doc_frequency(cfg, c.term_off, c.terms)
+    both = datagen.queries(cfg, df, n_queries=2 * cfg.n_queries)
+    qb = both.subset(range(cfg.n_queries))
+    tune = both.subset(range(cfg.n_queries, 2 * cfg.n_queries))
     k = 100
     sample = stratified(qb, args.sample)
     log(f"oracle on {len(sample)} stratified queries")
-    o, res, cpu_s = oracle_sample(c, qb, sample, lambda q: k)
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import OracleIndex
+    o = OracleIndex(cfg.dim, cfg.vocab)
+    o.load(c.emb, c.ids, c.term_off, c.terms)
+    o._posting_lists()
+    t0 = time.perf_counter()
+    workers = host_threads()[0]
+    with ThreadPoolExecutor(workers) as ex:
+        res = dict(zip(sample, ex.map(lambda q: o.search_one(qb.emb[q], qb.cnf(q), k), sample)))
+    cpu_s = time.perf_counter() - t0
     forms = {}
     for dt, r in (("f32", 0), ("bf16", 4096), ("fp8", 4096)):
-        log(f"{dt} index")
+        log(f"{dt} index, 10M")
         ix = Index(c.n, cfg.dim, cfg.vocab, k, dtype=dt, rescore_r=r, max_batch=qb.n,
                    n_workspaces=2)
         ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
-        til = ix.autotune(qb.emb, qb, k)
+        til = ix.autotune(tune.emb, tune, k)
         t = timed_search(torch, ix, qb, k, args.steps, args.warmup)
         st = t["stats"]
-        peak = {"f32": PEAKS["f32"], "bf16": PEAKS["bf16"], "fp8": PEAKS["fp8"]}[dt]
-        tf = 2.0 * cfg.dim * qb.n * st.n_live / (t["scan_ms"] * 1e-3) / 1e12
         f = {"qps": round(t["qps"], 1), "scan_ms": round(t["scan_ms"], 3),
              "search_ms_device": round(t["total_ms"], 3), "tiling": list(til),
-             "mfma_tflops": round(tf, 1), "mfma_frac": round(tf / peak, 4),
-             "hbm_gbs_alg": round(st.alg_bytes / (t["total_ms"] * 1e-3) / 1e9, 1),
-             "candidates_per_query": round(st.candidates / qb.n, 1), "rescore_r": r}
+             "candidates_per_query": round(st.candidates / qb.n, 1), "rescore_r": r,
+             "failed_queries": int(np.sum(t["count"] == 0xFFFFFFFF)),
+             "roofline": scan_roofline(c, dt, qb.n, st, t["scan_ms"])}
         f.update(precision_report(o, qb, res, t["ids"], t["scores"], t["count"], lambda q: k))
         forms[dt] = f
         ix.close()
     for dt in ("bf16", "fp8"):
         forms[dt]["vs_f32_qps"] = round(forms[dt]["qps"] / forms["f32"]["qps"], 3)
+    return {"workload": f"precision: {c.n:,} docs x {cfg.dim}-d, vocab {cfg.vocab}, {qb.n} "
+                        f"queries at 1%-50% selectivity, K=100, R=4096", "n_docs": c.n,
+            "forms": forms, "oracle_queries": len(sample),
+            "oracle_s_per_query_threads": round(cpu_s / max(1, len(sample)), 3),
+            "oracle_threads": workers}
+
+
+def bench_precision(args, torch):
+    leg = precision_leg(args, torch, args.n_docs)
     line = {"metric": "filtered top-K QPS, BF16/FP8 vs FP32 at recall@100", "config": {
-        "workload": f"precision: {c.n:,} docs x {cfg.dim}-d, vocab {cfg.vocab}, {qb.n} queries "
-                    f"at 1%-50% selectivity, K=100, R=4096", "n_docs": c.n},
-        "forms": forms, "cpu_oracle_s_per_query": round(cpu_s / len(sample), 3),
-        "data": "synthetic"}
+        "workload": leg["workload"], "n_docs": leg["n_docs"]}, "forms": leg["forms"],
+        "oracle_s_per_query_threads": leg["oracle_s_per_query_threads"], "data": "synthetic"}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -496,13 +539,13 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run an elementwise kernel that reads and "
                          "writes 1 GiB (known traffic, to scale HBM counter readings)")
-    # The FP32 workload's tiling is fixed: 8 compute wavefronts of one
-    # 32-query block each (two per SIMD, so one's epilogue overlaps the
-    # other's matrix work) and 4 groups per work item (245 items for 256
-    # workgroups) was the fastest of a sweep; autotuning picks between
-    # near-equal tilings by run-to-run noise.
-    ap.add_argument("--tiling", default="1,8,4",
-                    help="query_blocks,waves,groups_per_item for the FP32 path, or 'auto'")
+    ap.add_argument("--tiling", default="auto",
+                    help="query_blocks,waves,groups_per_item for the FP32 path, or 'auto' "
+                         "(the autotuner, on a disjoint batch of the same shape)")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 10M x 256 precision leg of the default run")
+    ap.add_argument("--c3-after-s", type=float, default=240.0,
+                    help="skip the precision leg when the run has already taken this long")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the retrieval path runs on a single MI355X "
@@ -523,14 +566,20 @@ def main() -> int:
         return bench_qsweep(args, torch)
     if args.config == "serving":
         return bench_serving(args, torch)
-    log("generating the fp32 workload (1M docs x 128, 256 queries)")
+    t_start = time.perf_counter()
+    log("generating the fp32 workload (1M docs x 128, 256 queries + a tuning batch)")
     c, qb = datagen.workload("fp32")
     k = 100
+    n_q = qb.n
+    # a second batch of the same recipe (queries 256..511), disjoint from
+    # the timed one: the autotuner and the forms' rescoring depth are chosen
+    # on it
+    df = datagen.doc_frequency(c.cfg, c.term_off, c.terms)
+    tune = datagen.queries(c.cfg, df, n_queries=2 * n_q).subset(range(n_q, 2 * n_q))
     log("FP32 path")
     tiling = (tuple(int(x) for x in args.tiling.split(","))
               if args.tiling and args.tiling != "auto" else None)
-    f32 = run_form(torch, c, qb, k, "f32", args.steps, args.warmup, tiling=tiling)
-    n_q = qb.n
+    f32 = run_form(torch, c, qb, k, "f32", args.steps, args.warmup, tiling=tiling, tune=tune)
     qps = n_q * args.steps / f32["elapsed"]
     st = f32["stats"]
     scan_avg_ms = float(np.mean(f32["scan_ms"]))
@@ -565,7 +614,9 @@ def main() -> int:
         "qps_host_buffers": round(f32["host_qps"], 1),
         "candidates_per_query": round(st.candidates / n_q, 1),
         "tiling": {"query_blocks": f32["tiling"][0], "waves": f32["tiling"][1],
-                   "groups_per_item": f32["tiling"][2]},
+                   "groups_per_item": f32["tiling"][2],
+                   "strategy": f32["tiling"][3] if len(f32["tiling"]) > 3 else None,
+                   "chosen_by": "pinned" if tiling else "autotuner (disjoint batch)"},
     }
     if args.copy_calibration:
         n = 1 << 28                                    # 1 GiB of float32
@@ -591,10 +642,8 @@ def main() -> int:
         # against the oracle.  A form's QPS is the median of three timed
         # blocks of --steps searches.
         forms = {}
-        tune_res, tune = {}, None
+        tune_res = {}
         if o is not None:
-            df = datagen.doc_frequency(c.cfg, c.term_off, c.terms)
-            tune = datagen.queries(c.cfg, df, n_queries=2 * n_q).subset(range(n_q, 2 * n_q))
             from concurrent.futures import ThreadPoolExecutor
             with ThreadPoolExecutor(host_threads()[0]) as ex:
                 tres = list(ex.map(lambda q: o.search_one(tune.emb[q], tune.cnf(q), k),
@@ -602,7 +651,7 @@ def main() -> int:
             tune_res = dict(enumerate(tres))
         for dt in ("bf16", "fp8"):
             tried, chosen = [], 1024
-            if tune is not None:
+            if tune_res:
                 for r_depth in (100, 128, 256, 512, 1024):
                     log(f"{dt} form, tuning R={r_depth}")
                     r = run_form(torch, c, tune, k, dt, 2, 1, rescore_r=r_depth, tiling=(0, 0, 0),
@@ -617,14 +666,16 @@ def main() -> int:
                         break
             log(f"{dt} form, R={chosen}")
             r = run_form(torch, c, qb, k, dt, args.steps, args.warmup, rescore_r=chosen,
-                         blocks=3)
+                         blocks=3, tune=tune)
             f = {"qps": round(n_q * args.steps / r["elapsed"], 1),
                  "scan_ms": round(float(np.mean(r["scan_ms"])), 4),
                  "search_ms_device": round(float(np.mean(r["total_ms"])), 4),
                  "rescore_r": chosen,
                  "tiling": list(r["tiling"]),
                  "candidates_per_query": round(r["stats"].candidates / n_q, 1),
-                 "vs_f32_qps": round((n_q * args.steps / r["elapsed"]) / qps, 3)}
+                 "vs_f32_qps": round((n_q * args.steps / r["elapsed"]) / qps, 3),
+                 "roofline": scan_roofline(c, dt, n_q, r["stats"],
+                                           float(np.mean(r["scan_ms"])))}
             if oracle_res:
                 rep = precision_report(o, qb, oracle_res, r["res"][0], r["res"][1],
                                        r["res"][2], lambda q: k)
@@ -635,6 +686,13 @@ def main() -> int:
             f["r_tuning"] = tried
             forms[dt] = f
         line["forms"] = forms
+    if not args.no_c3:
+        spent = time.perf_counter() - t_start
+        if spent > args.c3_after_s:
+            line["forms_10M"] = {"skipped": f"run already took {spent:.0f} s"}
+        else:
+            del c
+            line["forms_10M"] = precision_leg(args, torch)
     print(json.dumps(line), flush=True)
     if line.get("parity", {}).get("failed"):
         log(f"FP32 parity failures: {line['parity']}")

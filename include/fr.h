@@ -281,13 +281,49 @@ fr_status fr_debug_candidates(fr_index* ix, uint32_t n_q, uint32_t* out_ids,
 fr_status fr_set_tiling(fr_index* ix, uint32_t query_blocks, uint32_t waves,
                         uint32_t groups_per_item);
 
-/* Time every scan tiling this build has for the index's dtype and
- * dimension on the given batch (host pointers; each candidate runs three
- * searches, outputs are scratch) and keep the fastest.  The out_* pointers
- * (may be NULL) receive the choice (0 = per-batch default for the groups). */
+/* Search strategies (bits of fr_set_strategy and of the autotuner's
+ * choice; 0 = both features on).  FR_STRAT_NO_SPECULATION: start every
+ * query from the safe threshold (the K'-th best of the sample) instead of the
+ * tighter speculative one (see fr_search).  FR_STRAT_NO_REFRESH: the scan
+ * does not raise thresholds from the candidates it has found (the bucket
+ * histogram of the appendix's "Fast Top K Selection"); they stay at their
+ * start.  Results are identical under every strategy. */
+#define FR_STRAT_NO_SPECULATION 1u
+#define FR_STRAT_NO_REFRESH     2u
+
+/* Set the search strategy: with `pinned` nonzero it is used for every search;
+ * otherwise it is the default that tuned choices override.  FR_EINVAL for
+ * unknown bits. */
+fr_status fr_set_strategy(fr_index* ix, uint32_t strategy, int pinned);
+
+/* The autotuner of the batch form (appendix, "Batch Inference": the batch
+ * size trades latency for throughput; here the tile shape, the items and the
+ * selection strategy are tuned per batch shape).  On the given batch (host
+ * pointers; every trial runs six searches and keeps the median device time
+ * of the last five; outputs are scratch) it times every scan tiling this
+ * build has for the index's dtype and dimension with the default strategy,
+ * then the other strategies with the fastest tiling.  The winner is recorded
+ * in the index's tuning table under (device arch, dtype, dimension, vocabulary,
+ * ceil(log2 n_q), ceil(log2 of the largest K'), floor(-log2 of the median
+ * selectivity)); searches without a pinned tiling use the table entry of
+ * their Q and K' buckets (of several selectivity buckets, the one nearest the
+ * last measured).  Pinned tilings and strategies are left as they were.  The
+ * out_* pointers (may be NULL) receive the choice (groups 0 = per-batch
+ * default). */
 fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr_cnf_batch* cnf,
                       const uint32_t* k, uint32_t flags, uint32_t* out_query_blocks,
-                      uint32_t* out_waves, uint32_t* out_groups);
+                      uint32_t* out_waves, uint32_t* out_groups, uint32_t* out_strategy);
+
+/* Write the tuning table as JSON lines (one object per entry: arch, dtype,
+ * dim, vocab, q_bucket, k_bucket, sel_bucket, query_blocks, waves,
+ * groups_per_item, strategy, ms) to `path`, replacing the file. */
+fr_status fr_tuning_save(fr_index* ix, const char* path);
+
+/* Add the entries of a file written by fr_tuning_save that match this
+ * index (same arch, dtype, dim and vocab, and a tiling this build has) to its
+ * tuning table; other lines are skipped.  `out_loaded` (may be NULL)
+ * receives how many were added. */
+fr_status fr_tuning_load(fr_index* ix, const char* path, uint32_t* out_loaded);
 
 #ifdef __cplusplus
 }

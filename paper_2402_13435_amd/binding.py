@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_ECAPACITY"
                 -4: "FR_EDUPID", -5: "FR_ENOTFOUND", -6: "FR_EUNSUPPORTED",
                 -7: "FR_EDEVICE", -8: "FR_EBUSY"}
 FR_DEVICE_PTRS, FR_NOWAIT, FR_GRAPH, FR_ASYNC = 1, 2, 4, 8
+FR_STRAT_NO_SPECULATION, FR_STRAT_NO_REFRESH = 1, 2
 DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -83,7 +84,10 @@ SYMBOLS = {
     "fr_debug_candidates": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp]),
     "fr_set_tiling": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]),
     "fr_autotune": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.POINTER(FrCnfBatch), _vp,
-                                   ctypes.c_uint32, _u32p, _u32p, _u32p]),
+                                   ctypes.c_uint32, _u32p, _u32p, _u32p, _u32p]),
+    "fr_set_strategy": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_int]),
+    "fr_tuning_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "fr_tuning_load": (ctypes.c_int, [_vp, ctypes.c_char_p, _u32p]),
 }
 
 
@@ -356,15 +360,29 @@ class Index:
     def set_tiling(self, query_blocks: int = 0, waves: int = 0, groups_per_item: int = 0) -> None:
         _check(lib().fr_set_tiling(self._h, query_blocks, waves, groups_per_item))
 
-    def autotune(self, queries, cnf, k) -> Tuple[int, int, int]:
-        """Pick the fastest scan tiling for this batch; returns (query_blocks,
-        waves, groups_per_item)."""
+    def set_strategy(self, strategy: int = 0, pinned: bool = True) -> None:
+        _check(lib().fr_set_strategy(self._h, strategy, 1 if pinned else 0))
+
+    def autotune(self, queries, cnf, k) -> Tuple[int, int, int, int]:
+        """Tune the scan tiling and search strategy for this batch's shape;
+        the choice goes into the index's tuning table (used by later searches
+        without a pinned tiling).  Returns (query_blocks, waves,
+        groups_per_item, strategy)."""
         cnf = Cnf.of(cnf)
         n_q = cnf.n_queries
         q = _host(queries, np.float32).reshape(n_q, self.dim)
         k = _host(np.broadcast_to(np.asarray(k, dtype=np.uint32), (n_q,)), np.uint32)
-        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        a, b, c, d = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
         st = cnf.struct()
         _check(lib().fr_autotune(self._h, n_q, _ptr(q), ctypes.byref(st), _ptr(k), 0,
-                                 ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return int(a.value), int(b.value), int(c.value)
+                                 ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                 ctypes.byref(d)))
+        return int(a.value), int(b.value), int(c.value), int(d.value)
+
+    def tuning_save(self, path: str) -> None:
+        _check(lib().fr_tuning_save(self._h, os.fsencode(path)))
+
+    def tuning_load(self, path: str) -> int:
+        n = ctypes.c_uint32()
+        _check(lib().fr_tuning_load(self._h, os.fsencode(path), ctypes.byref(n)))
+        return int(n.value)

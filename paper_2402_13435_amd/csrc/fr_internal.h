@@ -32,6 +32,12 @@ constexpr int kSeedKeysMax = kSeedGroupsMax * (kGroup / kTile) * 4;
 // best, r = mu + t + 1, is below the K'-th best of all matches except with
 // that probability, and a failure is detected after the pass.
 constexpr float kSpecL = 9.2103404f;
+// Search strategies (bits; 0 = both features on), chosen by the autotuner:
+// no speculative starting threshold (start from the safe one), and no
+// threshold refresh by the keeper during the scan (thresholds stay at their
+// start).
+constexpr uint32_t kStratNoSpec = 1u;
+constexpr uint32_t kStratNoRefresh = 2u;
 constexpr int kLits = 12;            // literals per query in the scan's fast mask path
 // device scratch of fr_search_noalloc (one array per device, in the code
 // object) and the device ordinals it is looked up for
@@ -169,6 +175,7 @@ struct SeedArgs {
   uint32_t* tsafe;         // safe start when tau's start is speculative, else 0
   float* hlo;              // histogram range of the scan (narrowed here)
   float* hinvw;
+  uint32_t strategy;       // kStrat* bits
 };
 
 struct ScanArgs {
@@ -195,6 +202,7 @@ struct ScanArgs {
   uint32_t gpi;            // groups per work item
   const uint64_t* mw;      // predicate masks of the pass (see MaskWordArgs)
   uint32_t ppad;
+  uint32_t strategy;       // kStrat* bits
 };
 
 // Exact selection of a pass's candidates.  The first pass also sets up the

@@ -923,7 +923,7 @@ __global__ __launch_bounds__(kSeedSelThreads) void k_seed_select(SeedArgs a) {
   // of the query's matches that lie in the sample
   uint32_t r = kp;
   const double m_all = (double)a.nmatch[q];
-  if (m_all > 0.0 && ms > 0u) {
+  if (m_all > 0.0 && ms > 0u && !(a.strategy & kStratNoSpec)) {
     const float p = fminf(1.f, (float)((double)ms / m_all));
     const float mu = (float)kp * p;
     const float l3 = 2.f * kSpecL / 3.f;
@@ -1296,6 +1296,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     uint32_t rc[RJ][16];          // coarse, then fine counts
     uint32_t rtau[RJ], rcut[RJ], rsuf[RJ];
     auto refresh_issue = [&]() {
+      if (a.strategy & kStratNoRefresh) return;   // thresholds stay at their start
       if (rstage == 0) {
         rsel = 0;
 #pragma unroll

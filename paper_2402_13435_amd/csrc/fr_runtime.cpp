@@ -9,7 +9,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
 #include <functional>
+#include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <queue>
@@ -131,7 +134,7 @@ struct Workspace {
   // extent / output binding
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  uint64_t gkey[9] = {};
+  uint64_t gkey[10] = {};
   bool in_flight = false;
   uint32_t last_nq = 0;
   double last_alg_bytes = 0, last_alg_flops = 0;
@@ -150,6 +153,18 @@ struct fr_index {
   uint32_t seed_groups = 0;   // corpus groups sampled for starting thresholds
   int n_cu = 0, n_wg = 0;
   int qb = 0, nw = 0, gpi = 0;   // 0: chosen per batch
+  uint32_t strat = 0;             // search strategy bits (FR_STRAT_*)
+  bool strat_pinned = false;      // fr_set_strategy was called
+  // autotuned choices keyed by (Q bucket, K' bucket, selectivity bucket);
+  // the index's arch, dtype, dimension and vocabulary complete the key
+  struct Tuned {
+    int qb, nw, gpi;
+    uint32_t strat;
+    float ms;
+  };
+  std::map<std::tuple<int, int, int>, Tuned> tuned;
+  int last_sel = -1;              // selectivity bucket of the last host-output search
+  char arch[32] = {};
   hipStream_t stream = nullptr;
   std::vector<void*> dev_owned, host_owned;
   // corpus
@@ -389,11 +404,6 @@ fr_status write_docs(fr_index* ix, uint64_t n, const float* emb, const uint32_t*
 // group.  Default: the largest such tile that the batch fills (rounded up to
 // 128 queries), preferring eight wavefronts (two per SIMD).
 void pick_tiling(const fr_index* ix, uint32_t n_q, int* qb, int* nw) {
-  if (ix->qb && ix->nw) {
-    *qb = ix->qb;
-    *nw = ix->nw;
-    return;
-  }
   const uint32_t want = round_up(std::max<uint32_t>(n_q, 1), 128);
   int bq = 1, bw = 4;
   uint32_t best = 0;
@@ -412,13 +422,65 @@ void pick_tiling(const fr_index* ix, uint32_t n_q, int* qb, int* nw) {
   *nw = bw;
 }
 
-// Groups per work item: about two items per workgroup, so that most groups'
-// predicate masks are computed under the previous group's matrix work.
-int pick_gpi(const fr_index* ix, uint32_t n_q, int qt, uint32_t n_groups) {
-  if (ix->gpi) return ix->gpi;
-  const uint64_t qtiles = (n_q + qt - 1) / qt;
-  const uint64_t g = ((uint64_t)n_groups * qtiles + ix->n_wg) / (2ull * ix->n_wg);
-  return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 16));
+
+// Buckets of the tuning table: ceil(log2 n_q), ceil(log2 of the largest
+// selection size K'), and floor(-log2) of the median selectivity (0..20).
+int q_bucket(uint32_t n_q) {
+  int b = 0;
+  while ((1u << b) < std::max<uint32_t>(n_q, 1) && b < 31) ++b;
+  return b;
+}
+uint32_t sel_size(const fr_index* ix, uint32_t k) {
+  if (ix->dt == kF32 || !k) return k;
+  return std::max(k, std::min(ix->r, std::max(ix->r_min, 4u * k)));
+}
+int sel_bucket(double sel) {
+  if (!(sel > 0.0)) return 20;
+  return (int)std::min(20.0, std::max(0.0, std::floor(-std::log2(sel))));
+}
+
+// Tiling and strategy of one search: a pinned choice (fr_set_tiling /
+// fr_set_strategy), else the tuning table's entry for the batch's Q and K'
+// buckets (of several selectivity buckets, the one nearest the last
+// measured), else the per-batch defaults.
+struct Choice {
+  int qb, nw, gpi;
+  uint32_t strat;
+};
+Choice choose(const fr_index* ix, uint32_t n_q, const uint32_t* k, uint32_t n_groups) {
+  Choice c{1, 4, 0, ix->strat};
+  uint32_t kmax = 0;
+  for (uint32_t q = 0; q < n_q; ++q) kmax = std::max(kmax, sel_size(ix, k[q]));
+  const int qk = q_bucket(n_q), kk = q_bucket(kmax);
+  const fr_index::Tuned* hit = nullptr;
+  int best_d = 1 << 30;
+  for (const auto& e : ix->tuned) {
+    if (std::get<0>(e.first) != qk || std::get<1>(e.first) != kk) continue;
+    const int d = ix->last_sel < 0 ? 0 : std::abs(std::get<2>(e.first) - ix->last_sel);
+    if (d < best_d) {
+      best_d = d;
+      hit = &e.second;
+    }
+  }
+  if (ix->qb && ix->nw) {
+    c.qb = ix->qb;
+    c.nw = ix->nw;
+    c.gpi = ix->gpi;
+  } else if (hit) {
+    c.qb = hit->qb;
+    c.nw = hit->nw;
+    c.gpi = hit->gpi;
+    if (!ix->strat_pinned) c.strat = hit->strat;
+  } else {
+    pick_tiling(ix, n_q, &c.qb, &c.nw);
+    c.gpi = ix->gpi;
+  }
+  if (!c.gpi) {
+    const uint64_t qtiles = (n_q + 32u * c.qb * c.nw - 1) / (32u * c.qb * c.nw);
+    const uint64_t g = ((uint64_t)n_groups * qtiles + ix->n_wg) / (2ull * ix->n_wg);
+    c.gpi = (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 16));
+  }
+  return c;
 }
 
 // Per-query state of a search (thresholds, histograms, lists, literal
@@ -479,7 +541,7 @@ MaskWordArgs mask_args(const fr_index* ix, Workspace& w, uint32_t n_groups) {
   return ma;
 }
 
-fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int nw, int gpi,
+fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice& ch,
                          uint32_t n_groups, bool timing, const float* qsrc, uint32_t* o_ids,
                          float* o_scores, uint32_t* o_count, unsigned long long* o_nmatch) {
   // query rows: the workspace's padded copy (host queries), or the caller's
@@ -521,6 +583,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sd.nmatch = w.nmatch;
   sd.tau = w.tau;
   sd.tsafe = w.tsafe;
+  sd.strategy = ch.strat;
   sd.hlo = w.hlo;
   sd.hinvw = w.hinvw;
   FR_HIP(launch_seed(sd, ix->dt, ix->dpad, s));
@@ -546,11 +609,12 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   sa.cand_key = w.cand_key;
   sa.cap = w.cand_cap;
   sa.work = w.work;
-  sa.gpi = (uint32_t)gpi;
+  sa.gpi = (uint32_t)ch.gpi;
+  sa.strategy = ch.strat;
   sa.mw = w.mw;
   sa.ppad = ma.ppad;
   if (timing) FR_HIP(hipEventRecord(w.e_scan0, s));
-  FR_HIP(launch_scan(sa, ix->dt, ix->dpad, qb, nw, ix->n_wg, s));
+  FR_HIP(launch_scan(sa, ix->dt, ix->dpad, ch.qb, ch.nw, ix->n_wg, s));
   if (timing) FR_HIP(hipEventRecord(w.e_scan1, s));
 
   SelectArgs se{};
@@ -599,7 +663,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, int qb, int 
   ScanArgs sb = sa;
   sb.qlist = w.qlist2;
   sb.n_list = w.desc + 2;
-  FR_HIP(launch_scan(sb, ix->dt, ix->dpad, qb, nw, ix->n_wg, s));
+  FR_HIP(launch_scan(sb, ix->dt, ix->dpad, ch.qb, ch.nw, ix->n_wg, s));
   SelectArgs sf = se;
   sf.qlist = w.qlist2;
   sf.n_list = w.desc + 2;
@@ -780,6 +844,12 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess)
     return fail(FR_EDEVICE, "hipGetDeviceProperties failed");
   ix->n_cu = prop.multiProcessorCount;
+  {
+    size_t i = 0;
+    for (; i + 1 < sizeof ix->arch && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i)
+      ix->arch[i] = prop.gcnArchName[i];
+    ix->arch[i] = 0;
+  }
   ix->n_wg = std::max(kXcds, ix->n_cu / kXcds * kXcds);
   if (hipStreamCreateWithFlags(&ix->stream, hipStreamNonBlocking) != hipSuccess)
     return fail(FR_EDEVICE, "hipStreamCreate failed");
@@ -1081,24 +1151,21 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   float* o_scores = dev ? out_scores : w->out_scores;
   uint32_t* o_count = dev ? out_count : w->out_count;
   unsigned long long* o_nm = dev ? (unsigned long long*)out_nmatch : w->out_nmatch;
-  int qb = 1, nw = 4;
-  pick_tiling(ix, n_q, &qb, &nw);
   const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
-  const int gpi = pick_gpi(ix, n_q, 32 * qb * nw, n_groups);
+  const Choice ch = choose(ix, n_q, k, n_groups);
   ring_slot(ix, *w);
   if (flags & FR_GRAPH) {
     // the whole device sequence as one graph, captured once per tiling,
     // corpus extent and output binding; kernels read the batch size from the
     // workspace descriptor, so any batch reuses the graph
-    const uint64_t key[9] = {(uint64_t)qb, (uint64_t)nw, (uint64_t)gpi, n_groups,
+    const uint64_t key[10] = {(uint64_t)ch.qb, (uint64_t)ch.nw, (uint64_t)ch.gpi, n_groups,
                              (uint64_t)(uintptr_t)o_ids, (uint64_t)(uintptr_t)o_scores,
                              (uint64_t)(uintptr_t)o_count, (uint64_t)(uintptr_t)o_nm,
-                             (uint64_t)(uintptr_t)qsrc};
+                             (uint64_t)(uintptr_t)qsrc, (uint64_t)ch.strat};
     if (!w->gexec || std::memcmp(key, w->gkey, sizeof key) != 0) {
       drop_graph(*w);
       FR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      st = enqueue_search(ix, *w, s, qb, nw, gpi, n_groups, false, qsrc, o_ids, o_scores, o_count,
-                          o_nm);
+      st = enqueue_search(ix, *w, s, ch, n_groups, false, qsrc, o_ids, o_scores, o_count, o_nm);
       hipGraph_t g = nullptr;
       const hipError_t ce = hipStreamEndCapture(s, &g);
       if (st != FR_OK) return st;
@@ -1112,8 +1179,7 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
     FR_HIP(hipEventRecord(w->e_scan1, s));
     FR_HIP(hipEventRecord(w->e_end, s));
   } else {
-    st = enqueue_search(ix, *w, s, qb, nw, gpi, n_groups, true, qsrc, o_ids, o_scores, o_count,
-                        o_nm);
+    st = enqueue_search(ix, *w, s, ch, n_groups, true, qsrc, o_ids, o_scores, o_count, o_nm);
     if (st != FR_OK) return st;
   }
   const size_t kk = (size_t)n_q * ix->cfg.k_max;
@@ -1151,6 +1217,11 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
     std::memcpy(out_scores, w->h_scores, kk * 4);
     std::memcpy(out_count, w->h_count, n_q * 4);
     std::memcpy(out_nmatch, w->h_nmatch, n_q * 8);
+    if (ix->n_live) {
+      std::vector<uint64_t> nm(out_nmatch, out_nmatch + n_q);
+      std::nth_element(nm.begin(), nm.begin() + n_q / 2, nm.end());
+      ix->last_sel = sel_bucket((double)nm[n_q / 2] / (double)ix->n_live);
+    }
   }
   for (uint32_t q = 0; q < n_q; ++q) failed_q |= cnts[q] == 0xFFFFFFFFu;
   if (failed_q)
@@ -1207,11 +1278,9 @@ fr_status fr_search_noalloc(fr_index* ix, uint32_t n_q, const float* queries,
   if (st != FR_OK) return st;
   FR_HIP(hipEventRecord(ix->na_copied, s));
   ix->na_pending = true;
-  int qb = 1, nw = 4;
-  pick_tiling(ix, n_q, &qb, &nw);
-  const int gpi = pick_gpi(ix, n_q, 32 * qb * nw, n_groups);
-  st = enqueue_search(ix, w, s, qb, nw, gpi, n_groups, false, queries, out_ids, out_scores,
-                      out_count, (unsigned long long*)out_nmatch);
+  const Choice ch = choose(ix, n_q, k, n_groups);
+  st = enqueue_search(ix, w, s, ch, n_groups, false, queries, out_ids, out_scores, out_count,
+                      (unsigned long long*)out_nmatch);
   if (st != FR_OK) return st;
   if (async) return FR_OK;
   FR_HIP(hipMemcpyAsync(ix->na_h_count, out_count, (size_t)n_q * 4, hipMemcpyDeviceToHost, s));
@@ -1412,46 +1481,78 @@ fr_status fr_set_tiling(fr_index* ix, uint32_t query_blocks, uint32_t waves,
   return FR_OK;
 }
 
+fr_status fr_set_strategy(fr_index* ix, uint32_t strategy, int pinned) {
+  if (!ix) return fail(FR_EINVAL, "null index");
+  if (strategy & ~(uint32_t)(FR_STRAT_NO_SPECULATION | FR_STRAT_NO_REFRESH))
+    return fail(FR_EINVAL, "unknown strategy bits");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  ix->strat = strategy;
+  ix->strat_pinned = pinned != 0;
+  return FR_OK;
+}
+
 fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr_cnf_batch* cnf,
                       const uint32_t* k, uint32_t flags, uint32_t* out_query_blocks,
-                      uint32_t* out_waves, uint32_t* out_groups) {
+                      uint32_t* out_waves, uint32_t* out_groups, uint32_t* out_strategy) {
   if (!ix) return fail(FR_EINVAL, "null index");
   if (flags & FR_DEVICE_PTRS) return fail(FR_EINVAL, "autotune takes host pointers");
+  if (!n_q || !k) return fail(FR_EINVAL, "autotune needs a non-empty batch");
   const size_t kk = (size_t)n_q * ix->cfg.k_max;
   std::vector<uint32_t> ids(kk), cnt(n_q);
   std::vector<float> sc(kk);
   std::vector<uint64_t> nm(n_q);
-  float best = INFINITY;
-  int best_qb = 0, best_nw = 0, best_g = 0;
   const int saved_qb = ix->qb, saved_nw = ix->nw, saved_g = ix->gpi;
+  const uint32_t saved_strat = ix->strat;
+  const bool saved_pin = ix->strat_pinned;
+  auto restore = [&]() {
+    ix->qb = saved_qb;
+    ix->nw = saved_nw;
+    ix->gpi = saved_g;
+    ix->strat = saved_strat;
+    ix->strat_pinned = saved_pin;
+  };
+  // median device time of 5 searches (after one unmeasured) with the
+  // given tiling and strategy
+  auto timed = [&](int qb, int nw, int g, uint32_t strat, float* ms) -> fr_status {
+    ix->qb = qb;
+    ix->nw = nw;
+    ix->gpi = g;
+    ix->strat = strat;
+    ix->strat_pinned = true;
+    float t[5];
+    for (int rep = 0; rep < 6; ++rep) {
+      fr_status st = fr_search(ix, n_q, queries, cnf, k, ids.data(), sc.data(), cnt.data(),
+                               nm.data(), nullptr, 0);
+      if (st != FR_OK) return st;
+      fr_search_stats s{};
+      st = fr_stats(ix, &s);
+      if (st != FR_OK) return st;
+      if (rep) t[rep - 1] = s.ms_total;
+    }
+    std::sort(t, t + 5);
+    *ms = t[2];
+    return FR_OK;
+  };
   const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
+  float best = INFINITY;
+  int best_qb = 1, best_nw = 4, best_g = 0;
+  uint32_t best_s = 0;
+  // tilings with the default strategy, then the strategies with the best
+  // tiling
   for (int nw : {4, 8}) {
     for (int qb : {1, 2, 4}) {
       if (!scan_supported(ix->dt, ix->dpad, qb, nw)) continue;
       const uint32_t qt = 32u * qb * nw;
-      if (qt > round_up(std::max<uint32_t>(n_q, 1), 128) && qt > 128) continue;
-      ix->gpi = 0;
-      const int auto_g = pick_gpi(ix, n_q, (int)qt, n_groups);
+      if (qt > round_up(n_q, 128) && qt > 128) continue;
       for (int g : {0, 1, 2, 4, 8}) {
-        if (g && g == auto_g) continue;   // same as the per-batch default
-        ix->qb = qb;
-        ix->nw = nw;
-        ix->gpi = g;
-        float tot = 0;
-        for (int rep = 0; rep < 3; ++rep) {
-          fr_status st = fr_search(ix, n_q, queries, cnf, k, ids.data(), sc.data(), cnt.data(),
-                                   nm.data(), nullptr, 0);
-          if (st != FR_OK) {
-            ix->qb = saved_qb;
-            ix->nw = saved_nw;
-            ix->gpi = saved_g;
-            return st;
-          }
-          fr_search_stats s{};
-          if (fr_stats(ix, &s) == FR_OK && rep > 0) tot += s.ms_total;
+        float ms = 0;
+        fr_status st = timed(qb, nw, g, 0u, &ms);
+        if (st != FR_OK) {
+          restore();
+          return st;
         }
-        if (tot < best) {
-          best = tot;
+        if (ms < best) {
+          best = ms;
           best_qb = qb;
           best_nw = nw;
           best_g = g;
@@ -1459,12 +1560,88 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
       }
     }
   }
-  ix->qb = best_qb;
-  ix->nw = best_nw;
-  ix->gpi = best_g;
+  for (uint32_t strat : {FR_STRAT_NO_SPECULATION, FR_STRAT_NO_REFRESH,
+                         FR_STRAT_NO_SPECULATION | FR_STRAT_NO_REFRESH}) {
+    float ms = 0;
+    fr_status st = timed(best_qb, best_nw, best_g, strat, &ms);
+    if (st != FR_OK) {
+      restore();
+      return st;
+    }
+    if (ms < best) {
+      best = ms;
+      best_s = strat;
+    }
+  }
+  restore();
+  // the batch's buckets (its selectivity from the last search's counts)
+  uint32_t kmax = 0;
+  for (uint32_t q = 0; q < n_q; ++q) kmax = std::max(kmax, sel_size(ix, k[q]));
+  std::vector<uint64_t> m(nm);
+  std::nth_element(m.begin(), m.begin() + n_q / 2, m.end());
+  const int sb = sel_bucket(ix->n_live ? (double)m[n_q / 2] / (double)ix->n_live : 0.0);
+  {
+    std::lock_guard<std::mutex> lk(ix->mu);
+    ix->tuned[std::make_tuple(q_bucket(n_q), q_bucket(kmax), sb)] =
+        fr_index::Tuned{best_qb, best_nw, best_g, best_s, best};
+    ix->last_sel = sb;
+  }
+  (void)n_groups;
   if (out_query_blocks) *out_query_blocks = (uint32_t)best_qb;
   if (out_waves) *out_waves = (uint32_t)best_nw;
   if (out_groups) *out_groups = (uint32_t)best_g;
+  if (out_strategy) *out_strategy = best_s;
+  return FR_OK;
+}
+
+fr_status fr_tuning_save(fr_index* ix, const char* path) {
+  if (!ix || !path) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(FR_EINVAL, std::string("cannot write ") + path);
+  for (const auto& e : ix->tuned)
+    std::fprintf(f,
+                 "{\"arch\": \"%s\", \"dtype\": %d, \"dim\": %u, \"vocab\": %u, "
+                 "\"q_bucket\": %d, \"k_bucket\": %d, \"sel_bucket\": %d, "
+                 "\"query_blocks\": %d, \"waves\": %d, \"groups_per_item\": %d, "
+                 "\"strategy\": %u, \"ms\": %.4f}\n",
+                 ix->arch, ix->dt, ix->dim, ix->cfg.vocab, std::get<0>(e.first),
+                 std::get<1>(e.first), std::get<2>(e.first), e.second.qb, e.second.nw,
+                 e.second.gpi, e.second.strat, e.second.ms);
+  const bool ok = std::fclose(f) == 0;
+  if (!ok) return fail(FR_EINVAL, std::string("cannot write ") + path);
+  return FR_OK;
+}
+
+fr_status fr_tuning_load(fr_index* ix, const char* path, uint32_t* out_loaded) {
+  if (!ix || !path) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(FR_EINVAL, std::string("cannot read ") + path);
+  char line[512];
+  uint32_t n = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    char arch[32] = {};
+    int dt, qk, kk, sk, qb, nw, g;
+    unsigned dim, vocab, strat;
+    float ms;
+    const int got = std::sscanf(
+        line,
+        " {\"arch\": \"%31[^\"]\", \"dtype\": %d, \"dim\": %u, \"vocab\": %u, "
+        "\"q_bucket\": %d, \"k_bucket\": %d, \"sel_bucket\": %d, \"query_blocks\": %d, "
+        "\"waves\": %d, \"groups_per_item\": %d, \"strategy\": %u, \"ms\": %f}",
+        arch, &dt, &dim, &vocab, &qk, &kk, &sk, &qb, &nw, &g, &strat, &ms);
+    if (got != 12) continue;                    // not an entry line
+    if (std::strcmp(arch, ix->arch) || dt != ix->dt || dim != ix->dim || vocab != ix->cfg.vocab)
+      continue;                                 // tuned for another index shape
+    if (!scan_supported(ix->dt, ix->dpad, qb, nw) || g < 0 || g > 64 ||
+        (strat & ~(unsigned)(FR_STRAT_NO_SPECULATION | FR_STRAT_NO_REFRESH)))
+      continue;
+    ix->tuned[std::make_tuple(qk, kk, sk)] = fr_index::Tuned{qb, nw, g, strat, ms};
+    ++n;
+  }
+  std::fclose(f);
+  if (out_loaded) *out_loaded = n;
   return FR_OK;
 }
 

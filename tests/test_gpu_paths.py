@@ -91,18 +91,38 @@ def mixed():
     return c, qb, oracle_for(c)
 
 
-def test_mixed_k_f32_autotuned(mixed):
+def test_mixed_k_f32_autotuned(mixed, tmp_path):
+    """Every search strategy and the autotuned configuration give the default
+    configuration's rows bit for bit; the tuning table saved by one index is
+    loaded by another and used by its searches."""
+    from paper_2402_13435_amd.binding import FR_STRAT_NO_REFRESH, FR_STRAT_NO_SPECULATION
     c, qb, o = mixed
     ix = gpu_index(c, k_max=1000, max_batch=256)
     default = ix.search(qb.emb, qb, qb.k)
     for q in range(qb.n):
         check_query(o, qb, q, default, int(qb.k[q]))
+
+    def same(r):
+        return (np.array_equal(r.ids, default.ids) and np.array_equal(r.scores, default.scores)
+                and np.array_equal(r.count, default.count)
+                and np.array_equal(r.n_match, default.n_match))
+    for strat in (FR_STRAT_NO_SPECULATION, FR_STRAT_NO_REFRESH,
+                  FR_STRAT_NO_SPECULATION | FR_STRAT_NO_REFRESH):
+        ix.set_strategy(strat, pinned=True)
+        assert same(ix.search(qb.emb, qb, qb.k)), strat
+    ix.set_strategy(0, pinned=False)
     til = ix.autotune(qb.emb, qb, qb.k)
-    print(f"[paths] autotuned tiling {til}", flush=True)
-    tuned = ix.search(qb.emb, qb, qb.k)
-    assert np.array_equal(tuned.ids, default.ids) and np.array_equal(tuned.scores, default.scores)
-    assert np.array_equal(tuned.count, default.count)
+    print(f"[paths] autotuned (query_blocks, waves, groups, strategy) {til}", flush=True)
+    assert same(ix.search(qb.emb, qb, qb.k))
+    path = str(tmp_path / "tuning.jsonl")
+    ix.tuning_save(path)
     ix.close()
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and '"strategy": %d' % til[3] in lines[0]
+    ix2 = gpu_index(c, k_max=1000, max_batch=256)
+    assert ix2.tuning_load(path) == 1
+    assert same(ix2.search(qb.emb, qb, qb.k))
+    ix2.close()
 
 
 def test_mixed_k_bf16_rescore_min_graph(mixed):
