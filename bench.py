@@ -14,6 +14,7 @@ Prints one JSON line (see the repository's benchmark contract).
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import sys
@@ -40,7 +41,6 @@ def measured_traffic(workload: str, tiling) -> int | None:
     """HBM bytes per scan launch from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the scan source or the
     tiling differ from the ones the counters were taken with."""
-    import glob
     import hashlib
     import re
     src = os.path.join(ROOT, "paper_2402_13435_amd", "csrc", "fr_kernels.hip")
@@ -159,9 +159,19 @@ def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None, bl
     ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
     if tiling:
         ix.set_tiling(*tiling)
+        chosen_by = "pinned"
     else:
-        t = tune if tune is not None else qb
-        tiling = ix.autotune(t.emb, t, k)
+        # the shipped tuning table (written by paper_2402_13435_amd.tune on
+        # this GPU model) if it covers this batch shape, else the autotuner
+        for path in sorted(glob.glob(os.path.join(ROOT, "paper_2402_13435_amd", "tuning",
+                                                  "*.jsonl"))):
+            ix.tuning_load(path)
+        choice = ix.tuning_choice(qb.n, np.broadcast_to(np.asarray(k, np.uint32), (qb.n,)))
+        if choice[4] == 2:
+            tiling, chosen_by = choice[:4], "tuning table (paper_2402_13435_amd/tuning)"
+        else:
+            t = tune if tune is not None else qb
+            tiling, chosen_by = ix.autotune(t.emb, t, k), "autotuner (disjoint batch)"
     dev = torch.device("cuda:0")
     q = torch.from_numpy(qb.emb).to(dev)
     n_q = qb.n
@@ -198,7 +208,7 @@ def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None, bl
         host_qps = n_q * n_host / (time.perf_counter() - h0)
     ix.close()
     return {"elapsed": elapsed, "scan_ms": scan_ms, "total_ms": total_ms, "stats": stats,
-            "res": res, "tiling": tiling, "host_qps": host_qps}
+            "res": res, "tiling": tiling, "host_qps": host_qps, "chosen_by": chosen_by}
 
 
 def scan_roofline(c, dtype: str, n_q: int, stats, scan_ms: float) -> dict:
@@ -616,7 +626,7 @@ def main() -> int:
         "tiling": {"query_blocks": f32["tiling"][0], "waves": f32["tiling"][1],
                    "groups_per_item": f32["tiling"][2],
                    "strategy": f32["tiling"][3] if len(f32["tiling"]) > 3 else None,
-                   "chosen_by": "pinned" if tiling else "autotuner (disjoint batch)"},
+                   "chosen_by": f32["chosen_by"]},
     }
     if args.copy_calibration:
         n = 1 << 28                                    # 1 GiB of float32
@@ -650,7 +660,8 @@ def main() -> int:
                                    range(tune.n)))
             tune_res = dict(enumerate(tres))
         for dt in ("bf16", "fp8"):
-            tried, chosen = [], 1024
+            # without the oracle (--no-cpu): the depths this selection picks
+            tried, chosen = [], {"bf16": 100, "fp8": 128}[dt]
             if tune_res:
                 for r_depth in (100, 128, 256, 512, 1024):
                     log(f"{dt} form, tuning R={r_depth}")
@@ -671,7 +682,7 @@ def main() -> int:
                  "scan_ms": round(float(np.mean(r["scan_ms"])), 4),
                  "search_ms_device": round(float(np.mean(r["total_ms"])), 4),
                  "rescore_r": chosen,
-                 "tiling": list(r["tiling"]),
+                 "tiling": list(r["tiling"]), "tiling_chosen_by": r["chosen_by"],
                  "candidates_per_query": round(r["stats"].candidates / n_q, 1),
                  "vs_f32_qps": round((n_q * args.steps / r["elapsed"]) / qps, 3),
                  "roofline": scan_roofline(c, dt, n_q, r["stats"],

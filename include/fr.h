@@ -299,10 +299,11 @@ fr_status fr_set_strategy(fr_index* ix, uint32_t strategy, int pinned);
 /* The autotuner of the batch form (appendix, "Batch Inference": the batch
  * size trades latency for throughput; here the tile shape, the items and the
  * selection strategy are tuned per batch shape).  On the given batch (host
- * pointers; every trial runs six searches and keeps the median device time
- * of the last five; outputs are scratch) it times every scan tiling this
- * build has for the index's dtype and dimension with the default strategy,
- * then the other strategies with the fastest tiling.  The winner is recorded
+ * pointers; a trial is one unmeasured search and the median device time of
+ * the next ones; outputs are scratch) it times every scan tiling this build
+ * has for the index's dtype and dimension with the default strategy, then
+ * the other strategies with the three fastest tilings (3 searches per
+ * trial), and the three fastest trials again (9 searches each).  The winner is recorded
  * in the index's tuning table under (device arch, dtype, dimension, vocabulary,
  * ceil(log2 n_q), ceil(log2 of the largest K'), floor(-log2 of the median
  * selectivity)); searches without a pinned tiling use the table entry of
@@ -313,6 +314,14 @@ fr_status fr_set_strategy(fr_index* ix, uint32_t strategy, int pinned);
 fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr_cnf_batch* cnf,
                       const uint32_t* k, uint32_t flags, uint32_t* out_query_blocks,
                       uint32_t* out_waves, uint32_t* out_groups, uint32_t* out_strategy);
+
+/* The configuration a search of n_q queries with these K values (host)
+ * would use now: tiling, groups per item (resolved, never 0), strategy, and
+ * where it comes from (`out_source`: 0 the per-batch defaults, 1 a pinned
+ * tiling, 2 the tuning table).  Any output may be NULL. */
+fr_status fr_tuning_choice(fr_index* ix, uint32_t n_q, const uint32_t* k,
+                           uint32_t* out_query_blocks, uint32_t* out_waves,
+                           uint32_t* out_groups, uint32_t* out_strategy, uint32_t* out_source);
 
 /* Write the tuning table as JSON lines (one object per entry: arch, dtype,
  * dim, vocab, q_bucket, k_bucket, sel_bucket, query_blocks, waves,

@@ -87,6 +87,8 @@ SYMBOLS = {
                                    ctypes.c_uint32, _u32p, _u32p, _u32p, _u32p]),
     "fr_set_strategy": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_int]),
     "fr_tuning_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "fr_tuning_choice": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _u32p, _u32p, _u32p, _u32p,
+                                        _u32p]),
     "fr_tuning_load": (ctypes.c_int, [_vp, ctypes.c_char_p, _u32p]),
 }
 
@@ -378,6 +380,15 @@ class Index:
                                  ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                  ctypes.byref(d)))
         return int(a.value), int(b.value), int(c.value), int(d.value)
+
+    def tuning_choice(self, n_q: int, k):
+        """(query_blocks, waves, groups_per_item, strategy, source) a search of
+        n_q queries with these K would use; source 0 defaults, 1 pinned, 2
+        the tuning table."""
+        k = _host(np.broadcast_to(np.asarray(k, dtype=np.uint32), (n_q,)), np.uint32)
+        out = [ctypes.c_uint32() for _ in range(5)]
+        _check(lib().fr_tuning_choice(self._h, n_q, _ptr(k), *[ctypes.byref(o) for o in out]))
+        return tuple(int(o.value) for o in out)
 
     def tuning_save(self, path: str) -> None:
         _check(lib().fr_tuning_save(self._h, os.fsencode(path)))

@@ -446,9 +446,10 @@ int sel_bucket(double sel) {
 struct Choice {
   int qb, nw, gpi;
   uint32_t strat;
+  int source;   // 0 defaults, 1 pinned, 2 tuning table
 };
 Choice choose(const fr_index* ix, uint32_t n_q, const uint32_t* k, uint32_t n_groups) {
-  Choice c{1, 4, 0, ix->strat};
+  Choice c{1, 4, 0, ix->strat, 0};
   uint32_t kmax = 0;
   for (uint32_t q = 0; q < n_q; ++q) kmax = std::max(kmax, sel_size(ix, k[q]));
   const int qk = q_bucket(n_q), kk = q_bucket(kmax);
@@ -466,11 +467,13 @@ Choice choose(const fr_index* ix, uint32_t n_q, const uint32_t* k, uint32_t n_gr
     c.qb = ix->qb;
     c.nw = ix->nw;
     c.gpi = ix->gpi;
+    c.source = 1;
   } else if (hit) {
     c.qb = hit->qb;
     c.nw = hit->nw;
     c.gpi = hit->gpi;
     if (!ix->strat_pinned) c.strat = hit->strat;
+    c.source = 2;
   } else {
     pick_tiling(ix, n_q, &c.qb, &c.nw);
     c.gpi = ix->gpi;
@@ -1511,68 +1514,83 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
     ix->strat = saved_strat;
     ix->strat_pinned = saved_pin;
   };
-  // median device time of 5 searches (after one unmeasured) with the
+  // median device time of `reps` searches (after one unmeasured) with the
   // given tiling and strategy
-  auto timed = [&](int qb, int nw, int g, uint32_t strat, float* ms) -> fr_status {
+  auto timed = [&](int qb, int nw, int g, uint32_t strat, int reps, float* ms) -> fr_status {
     ix->qb = qb;
     ix->nw = nw;
     ix->gpi = g;
     ix->strat = strat;
     ix->strat_pinned = true;
-    float t[5];
-    for (int rep = 0; rep < 6; ++rep) {
+    std::vector<float> t;
+    for (int rep = 0; rep <= reps; ++rep) {
       fr_status st = fr_search(ix, n_q, queries, cnf, k, ids.data(), sc.data(), cnt.data(),
                                nm.data(), nullptr, 0);
       if (st != FR_OK) return st;
       fr_search_stats s{};
       st = fr_stats(ix, &s);
       if (st != FR_OK) return st;
-      if (rep) t[rep - 1] = s.ms_total;
+      if (rep) t.push_back(s.ms_total);
     }
-    std::sort(t, t + 5);
-    *ms = t[2];
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
     return FR_OK;
   };
-  const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
-  float best = INFINITY;
-  int best_qb = 1, best_nw = 4, best_g = 0;
-  uint32_t best_s = 0;
-  // tilings with the default strategy, then the strategies with the best
-  // tiling
+  struct Trial {
+    int qb, nw, g;
+    uint32_t strat;
+    float ms;
+  };
+  // Round 1: every tiling with the default strategy, then the other
+  // strategies with the three fastest tilings, 3 timed searches each.
+  // Round 2: the three fastest trials again with 9 timed searches each
+  // (near-equal candidates are told apart by the longer median).
+  std::vector<Trial> trials;
   for (int nw : {4, 8}) {
     for (int qb : {1, 2, 4}) {
       if (!scan_supported(ix->dt, ix->dpad, qb, nw)) continue;
       const uint32_t qt = 32u * qb * nw;
       if (qt > round_up(n_q, 128) && qt > 128) continue;
       for (int g : {0, 1, 2, 4, 8}) {
-        float ms = 0;
-        fr_status st = timed(qb, nw, g, 0u, &ms);
+        Trial t{qb, nw, g, 0u, 0.f};
+        fr_status st = timed(qb, nw, g, 0u, 3, &t.ms);
         if (st != FR_OK) {
           restore();
           return st;
         }
-        if (ms < best) {
-          best = ms;
-          best_qb = qb;
-          best_nw = nw;
-          best_g = g;
-        }
+        trials.push_back(t);
       }
     }
   }
-  for (uint32_t strat : {FR_STRAT_NO_SPECULATION, FR_STRAT_NO_REFRESH,
-                         FR_STRAT_NO_SPECULATION | FR_STRAT_NO_REFRESH}) {
-    float ms = 0;
-    fr_status st = timed(best_qb, best_nw, best_g, strat, &ms);
+  auto by_ms = [](const Trial& x, const Trial& y) { return x.ms < y.ms; };
+  std::sort(trials.begin(), trials.end(), by_ms);
+  const size_t n_top = std::min<size_t>(3, trials.size());
+  for (size_t i = 0; i < n_top; ++i) {
+    for (uint32_t strat : {FR_STRAT_NO_SPECULATION, FR_STRAT_NO_REFRESH,
+                           FR_STRAT_NO_SPECULATION | FR_STRAT_NO_REFRESH}) {
+      Trial t = trials[i];
+      t.strat = strat;
+      fr_status st = timed(t.qb, t.nw, t.g, strat, 3, &t.ms);
+      if (st != FR_OK) {
+        restore();
+        return st;
+      }
+      trials.push_back(t);
+    }
+  }
+  std::sort(trials.begin(), trials.end(), by_ms);
+  trials.resize(std::min<size_t>(3, trials.size()));
+  for (Trial& t : trials) {
+    fr_status st = timed(t.qb, t.nw, t.g, t.strat, 9, &t.ms);
     if (st != FR_OK) {
       restore();
       return st;
     }
-    if (ms < best) {
-      best = ms;
-      best_s = strat;
-    }
   }
+  std::sort(trials.begin(), trials.end(), by_ms);
+  const float best = trials[0].ms;
+  const int best_qb = trials[0].qb, best_nw = trials[0].nw, best_g = trials[0].g;
+  const uint32_t best_s = trials[0].strat;
   restore();
   // the batch's buckets (its selectivity from the last search's counts)
   uint32_t kmax = 0;
@@ -1586,11 +1604,25 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
         fr_index::Tuned{best_qb, best_nw, best_g, best_s, best};
     ix->last_sel = sb;
   }
-  (void)n_groups;
   if (out_query_blocks) *out_query_blocks = (uint32_t)best_qb;
   if (out_waves) *out_waves = (uint32_t)best_nw;
   if (out_groups) *out_groups = (uint32_t)best_g;
   if (out_strategy) *out_strategy = best_s;
+  return FR_OK;
+}
+
+fr_status fr_tuning_choice(fr_index* ix, uint32_t n_q, const uint32_t* k,
+                           uint32_t* out_query_blocks, uint32_t* out_waves,
+                           uint32_t* out_groups, uint32_t* out_strategy, uint32_t* out_source) {
+  if (!ix || (n_q && !k)) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
+  const Choice c = choose(ix, n_q, k, n_groups);
+  if (out_query_blocks) *out_query_blocks = (uint32_t)c.qb;
+  if (out_waves) *out_waves = (uint32_t)c.nw;
+  if (out_groups) *out_groups = (uint32_t)c.gpi;
+  if (out_strategy) *out_strategy = c.strat;
+  if (out_source) *out_source = (uint32_t)c.source;
   return FR_OK;
 }
 
