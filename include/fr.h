@@ -282,7 +282,7 @@ fr_status fr_set_tiling(fr_index* ix, uint32_t query_blocks, uint32_t waves,
                         uint32_t groups_per_item);
 
 /* Search strategies (bits of fr_set_strategy and of the autotuner's
- * choice; 0 = both features on).  FR_STRAT_NO_SPECULATION: start every
+ * choice; 0 = both features on; an index starts with FR_STRAT_NO_REFRESH).  FR_STRAT_NO_SPECULATION: start every
  * query from the safe threshold (the K'-th best of the sample) instead of the
  * tighter speculative one (see fr_search).  FR_STRAT_NO_REFRESH: the scan
  * does not raise thresholds from the candidates it has found (the bucket

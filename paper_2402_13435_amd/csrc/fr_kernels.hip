@@ -1846,7 +1846,37 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     select_rerun(a, q, 2u);
     return;
   }
-  const uint32_t tau = a.tau[q];
+  // Cut before sorting: the query's histogram counts exactly this pass's
+  // candidates, so the lower edge of the bucket below the one where the
+  // count from the top reaches kp is at most the kp-th best candidate
+  // (the same bucket rule as the scan's threshold refresh); candidates below
+  // max(tau, that edge) cannot be selected.
+  __shared__ uint32_t s_tau;
+  if (threadIdx.x == 0) {
+    uint32_t t = a.tau[q];
+    const uint32_t* h = a.hist + (uint64_t)q * kHist;
+    const float lo0 = a.hlo[q], iw0 = a.hinvw[q];
+    uint32_t suffix = 0;
+    int bstar = -1;
+    for (int cb = kNBC - 1; cb >= 0 && bstar < 0; --cb) {
+      if (suffix + h[cb] < kp) {
+        suffix += h[cb];
+        continue;
+      }
+      for (int f = 15; f >= 0; --f) {
+        suffix += h[kNBC + cb * 16 + f];
+        if (suffix >= kp) {
+          bstar = cb * 16 + f;
+          break;
+        }
+      }
+      if (bstar < 0) bstar = cb * 16;   // coarse and fine counts disagree: stay safe
+    }
+    if (kp && bstar >= 2 && iw0 > 0.f) t = max(t, fkey(lo0 + (float)(bstar - 1) / iw0));
+    s_tau = t;
+  }
+  __syncthreads();
+  const uint32_t tau = s_tau;
   const unsigned long long* ck = a.cand_key + (uint64_t)q * a.cap;
   // a candidate is stored as (score key, slot); its sort key is (score key,
   // complement of the slot's id)
@@ -1985,6 +2015,9 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
 // top-K by (FP32 score desc, id asc).
 __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
   __shared__ unsigned long long s_key[kMaxR];
+  __shared__ unsigned long long s_sur[kMaxR];   // keys that survive the bucket cut
+  __shared__ uint32_t s_cnt[256];
+  __shared__ uint32_t s_kmin, s_kmax, s_cut, s_n;
   const uint32_t q = blockIdx.x;
   if (q >= *a.n_dev) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -2037,14 +2070,65 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
       }
     }
   }
-  const int n2 = pow2_at_least((int)(m ? m : 1));
-  for (int i = (int)m + threadIdx.x; i < n2; i += blockDim.x) s_key[i] = 0ull;
   __syncthreads();
-  bitonic_desc(s_key, nullptr, n2);
   const uint32_t kq = min(a.k[q], m);
+  // Only the best kq keys are output: with many rows, keep the 256-bucket
+  // buckets (over the score keys' integer range, so bucket order is key
+  // order exactly) from the one holding the kq-th key upwards, and sort
+  // those survivors only.
+  unsigned long long* srt = s_key;
+  uint32_t n = m;
+  if (m > 512u && kq) {
+    if (threadIdx.x == 0) {
+      s_kmin = 0xFFFFFFFFu;
+      s_kmax = 0u;
+      s_n = 0u;
+    }
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) s_cnt[i] = 0u;
+    __syncthreads();
+    uint32_t lmin = 0xFFFFFFFFu, lmax = 0u;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+      const uint32_t hk = (uint32_t)(s_key[i] >> 32);
+      lmin = min(lmin, hk);
+      lmax = max(lmax, hk);
+    }
+    atomicMin(&s_kmin, lmin);
+    atomicMax(&s_kmax, lmax);
+    __syncthreads();
+    const uint32_t kmin = s_kmin;
+    const uint64_t span = (uint64_t)(s_kmax - kmin) + 1ull;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+      const uint32_t hk = (uint32_t)(s_key[i] >> 32);
+      atomicAdd(&s_cnt[(uint32_t)(((uint64_t)(hk - kmin) << 8) / span)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t cum = 0u;
+      int b = 255;
+      for (; b > 0; --b) {
+        cum += s_cnt[b];
+        if (cum >= kq) break;
+      }
+      // lower edge of bucket b: the least key whose bucket is b
+      s_cut = kmin + (uint32_t)(((uint64_t)b * span + 255ull) >> 8);
+    }
+    __syncthreads();
+    const uint32_t cut = s_cut;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+      const unsigned long long k = s_key[i];
+      if ((uint32_t)(k >> 32) >= cut) s_sur[atomicAdd(&s_n, 1u)] = k;
+    }
+    __syncthreads();
+    srt = s_sur;
+    n = s_n;
+  }
+  const int n2 = pow2_at_least((int)(n ? n : 1));
+  for (int i = (int)n + threadIdx.x; i < n2; i += blockDim.x) srt[i] = 0ull;
+  __syncthreads();
+  bitonic_desc(srt, nullptr, n2);
   for (uint32_t r = threadIdx.x; r < a.k_max; r += blockDim.x) {
     const bool ok = r < kq;
-    const unsigned long long k = ok ? s_key[r] : 0ull;
+    const unsigned long long k = ok ? srt[r] : 0ull;
     a.out_ids[(uint64_t)q * a.k_max + r] = ok ? 0xFFFFFFFFu - (uint32_t)k : 0xFFFFFFFFu;
     a.out_scores[(uint64_t)q * a.k_max + r] = ok ? key2f((uint32_t)(k >> 32)) : -INFINITY;
   }

@@ -820,6 +820,10 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   ix->rmax = ix->dt == kF32 ? cfg->k_max : ix->r;
   ix->qmax = cfg->max_batch ? cfg->max_batch : 1024;
   ix->seed_groups = ix->dt == kF32 ? kSeedGroupsF32 : kSeedGroupsLow;
+  // default strategy: speculative start, no threshold refresh during the
+  // scan (with the selection's own bucket cut the refresh costs more than
+  // the candidates it saves on the measured workloads)
+  ix->strat = FR_STRAT_NO_REFRESH;
   if (ix->qmax > 65536) return fail(FR_EINVAL, "max_batch must be <= 65536");
   ix->cmax = cfg->max_clauses ? cfg->max_clauses : 8 * ix->qmax;
   ix->lmax = cfg->max_literals ? cfg->max_literals : 32 * ix->qmax;
