@@ -324,6 +324,36 @@ def queries(cfg: Config, df: Optional[np.ndarray] = None,
 # serving workload
 # --------------------------------------------------------------------------
 
+@dataclasses.dataclass
+class SignProjection:
+    """Random draws of a sign-code quantiser: bit j sums the positions
+    bin_off[j] .. bin_off[j+1] of (bin_dim, bin_sign)."""
+    bin_off: np.ndarray           # u32 [n_bits + 1]
+    bin_dim: np.ndarray           # u32 [entries]
+    bin_sign: np.ndarray          # f32 [entries], each +1 or -1
+
+    @property
+    def n_bits(self) -> int:
+        return len(self.bin_off) - 1
+
+
+def sign_projection(dim: int, n_bits: int = 512, seed: int = 0,
+                    bin_size: Optional[int] = None) -> SignProjection:
+    """Independent random permutations of the ``dim`` coordinates,
+    concatenated and cut into ``n_bits`` bins of ``bin_size`` consecutive
+    positions, with a random sign per position.  Default bin size:
+    dim // n_bits when that is at least 2 (one permutation, equal bins),
+    else 2 (several permutations)."""
+    s = bin_size or (dim // n_bits if dim >= 2 * n_bits else 2)
+    need = n_bits * s
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([ROOT_SEED, 1000, seed])))
+    perms = [g.permutation(dim) for _ in range(-(-need // dim))]
+    dims = np.concatenate(perms)[:need].astype(np.uint32)
+    signs = np.where(g.random(need) < 0.5, -1.0, 1.0).astype(np.float32)
+    off = (np.arange(n_bits + 1, dtype=np.uint64) * s).astype(np.uint32)
+    return SignProjection(off, dims, signs)
+
+
 def arrivals(cfg: Config, rate_qps: float, n: int, level: int = 0) -> np.ndarray:
     """Poisson arrival times (seconds from 0) at ``rate_qps``."""
     seq = _children(cfg)[_S_ARR].spawn(level + 1)[level]
