@@ -30,6 +30,10 @@ PEAKS = {  # MI355X published dense peaks
     "f32": 157.3,      # TFLOP/s, FP32 matrix
     "bf16": 2500.0,
     "fp8": 5000.0,
+    # 32-bit vector ALU operations: 256 CUs x 64 lanes x 2.4 GHz (one
+    # operation per lane per clock; the 157.3 TFLOP/s FP32 vector figure
+    # counts an FMA as two and packed issue twice)
+    "valu_int32": 39.3,
 }
 
 
@@ -144,20 +148,28 @@ def check_parity(o, qb, k: int, oracle_res: dict, ids, scores, counts, nmatch) -
 
 
 def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None, blocks=1,
-             host=True, tune=None):
+             host=True, tune=None, preselect=None):
     """One index, warm-up searches, then `blocks` timed blocks of `steps`
     searches; the elapsed time reported is the median block's (the FP32
     benchmark line uses one block).  Without a pinned `tiling` the
     autotuner picks the tiling and search strategy on the batch `tune` (a
     disjoint batch of the same shape; `qb` itself if None) and later searches
-    use its choice through the index's tuning table."""
+    use its choice through the index's tuning table.  `preselect` =
+    (bits, factor) runs the sign-code pre-selection searches instead (codes
+    drawn by datagen.sign_projection, quantK = factor * k)."""
     from paper_2402_13435_amd import Index, SearchResult
     # two workspaces: the host prepares the next search while the device runs
     # the current one
+    qbits, qfactor = preselect or (0, 0)
     ix = Index(c.n, c.cfg.dim, c.cfg.vocab, k, dtype=dtype, rescore_r=rescore_r,
-               max_batch=qb.n, n_workspaces=2)
+               max_batch=qb.n, n_workspaces=2, quant_bits=qbits, quant_factor=qfactor)
     ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
-    if tiling:
+    if preselect:
+        import datagen
+        pr = datagen.sign_projection(c.cfg.dim, qbits, seed=0)
+        ix.set_quantizer(pr.bin_off, pr.bin_dim, pr.bin_sign)
+        tiling, chosen_by = (0, 0, 0, 0), "n/a (pre-selection)"
+    elif tiling:
         ix.set_tiling(*tiling)
         chosen_by = "pinned"
     else:
@@ -180,14 +192,15 @@ def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None, bl
                        torch.empty(n_q, dtype=torch.int32, device=dev),
                        torch.empty(n_q, dtype=torch.int64, device=dev))
     stream = torch.cuda.Stream()   # searches are asynchronous on their own stream
+    pre = preselect is not None
     for _ in range(warmup):
-        ix.search(q, qb, k, out=out, stream=stream)
+        ix.search(q, qb, k, out=out, stream=stream, preselect=pre)
     torch.cuda.synchronize()
     spans = []
     for _ in range(blocks):
         t0 = time.perf_counter()
         for _ in range(steps):
-            ix.search(q, qb, k, out=out, stream=stream)
+            ix.search(q, qb, k, out=out, stream=stream, preselect=pre)
         torch.cuda.synchronize()
         spans.append(time.perf_counter() - t0)
     elapsed = sorted(spans)[len(spans) // 2]
@@ -204,7 +217,7 @@ def run_form(torch, c, qb, k, dtype, steps, warmup, rescore_r=0, tiling=None, bl
         h0 = time.perf_counter()
         n_host = max(2, steps // 4)
         for _ in range(n_host):
-            ix.search(qb.emb, qb, k)
+            ix.search(qb.emb, qb, k, preselect=pre)
         host_qps = n_q * n_host / (time.perf_counter() - h0)
     ix.close()
     return {"elapsed": elapsed, "scan_ms": scan_ms, "total_ms": total_ms, "stats": stats,
@@ -229,6 +242,25 @@ def scan_roofline(c, dtype: str, n_q: int, stats, scan_ms: float) -> dict:
     return {"bound": "hbm" if f_hbm >= f_mma else "mfma", "scan_ms": round(scan_ms, 4),
             "alg_bytes": alg_bytes, "hbm_gbs": round(gbs, 1), "hbm_frac": round(f_hbm, 4),
             "mfma_tflops": round(tfs, 2), "mfma_frac": round(f_mma, 4)}
+
+
+def preselect_roofline(c, bits: int, res, stats, scan_ms: float) -> dict:
+    """The two code passes (histogram, collect) against the HBM roof (each
+    pass reads every live document's code, bits / 8 bytes, and one bit per
+    referenced term and per live document) and the vector-ALU roof (scoring
+    a matched (query, document) pair costs 4 32-bit operations per 64-bit
+    code word in each pass: two XNOR, two popcount-accumulate)."""
+    n = stats.n_live
+    alg_bytes = 2 * (n * bits / 8 + n * stats.n_terms_batch / 8.0 + n / 8.0)
+    pairs = float(np.sum(res[3].astype(np.float64)))
+    ops = 2 * pairs * 4 * (bits // 64)
+    t = scan_ms * 1e-3
+    gbs = alg_bytes / t / 1e9
+    tops = ops / t / 1e12
+    f_hbm, f_alu = gbs / PEAKS["hbm_gbs"], tops / PEAKS["valu_int32"]
+    return {"bound": "hbm" if f_hbm >= f_alu else "alu", "scan_ms": round(scan_ms, 4),
+            "alg_bytes": alg_bytes, "hbm_gbs": round(gbs, 1), "hbm_frac": round(f_hbm, 4),
+            "alg_int_ops": ops, "valu_tops": round(tops, 2), "alu_frac": round(f_alu, 4)}
 
 
 def stratified(qb, n: int):
@@ -265,7 +297,7 @@ def precision_report(o, qb, res, ids, scores, counts, k_of):
     return {"recall": round(rec, 5), "queries": len(got) - skipped, "max_score_err": err}
 
 
-def timed_search(torch, ix, qb, k, steps, warmup, graph=False):
+def timed_search(torch, ix, qb, k, steps, warmup, graph=False, preselect=False):
     from paper_2402_13435_amd import SearchResult
     dev = torch.device("cuda:0")
     q = torch.from_numpy(qb.emb).to(dev)
@@ -276,11 +308,11 @@ def timed_search(torch, ix, qb, k, steps, warmup, graph=False):
                        torch.empty(n_q, dtype=torch.int64, device=dev))
     stream = torch.cuda.Stream()   # searches are asynchronous on their own stream
     for _ in range(warmup):
-        ix.search(q, qb, k, out=out, stream=stream, graph=graph)
+        ix.search(q, qb, k, out=out, stream=stream, graph=graph, preselect=preselect)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ix.search(q, qb, k, out=out, stream=stream, graph=graph)
+        ix.search(q, qb, k, out=out, stream=stream, graph=graph, preselect=preselect)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     scan_ms, total_ms = ix.timings(steps)
@@ -288,7 +320,8 @@ def timed_search(torch, ix, qb, k, steps, warmup, graph=False):
     return {"elapsed": el, "qps": n_q * steps / el, "scan_ms": float(np.mean(scan_ms)),
             "total_ms": float(np.mean(total_ms)), "stats": st,
             "ids": out.ids.cpu().numpy().view(np.uint32), "scores": out.scores.cpu().numpy(),
-            "count": out.count.cpu().numpy().view(np.uint32)}
+            "count": out.count.cpu().numpy().view(np.uint32),
+            "n_match": out.n_match.cpu().numpy()}
 
 
 def precision_leg(args, torch, n_docs: int = 0):
@@ -407,12 +440,31 @@ def bench_qsweep(args, torch):
     big = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms), n_queries=1024)
     sizes = [int(x) for x in args.q_sizes.split(",")]
     points = []
-    for dt in ("f32", "bf16", "fp8"):
-        ix = Index(c.n, cfg.dim, cfg.vocab, 100, dtype=dt, rescore_r=128 if dt != "f32" else 0,
-                   max_batch=max(sizes), n_workspaces=2)
+    for dt in ("f32", "bf16", "fp8", "sign512"):
+        pre = dt == "sign512"
+        ix = Index(c.n, cfg.dim, cfg.vocab, 100, dtype="f32" if pre else dt,
+                   rescore_r=128 if dt in ("bf16", "fp8") else 0,
+                   max_batch=max(sizes), n_workspaces=2, quant_bits=512 if pre else 0)
         ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
+        if pre:
+            pr = datagen.sign_projection(cfg.dim, 512, seed=0)
+            ix.set_quantizer(pr.bin_off, pr.bin_dim, pr.bin_sign)
         for q in sizes:
             qb = big.subset(list(range(q)))
+            if pre:
+                # sign codes, quantK = 200 K, FP32 scores of the survivors
+                t = timed_search(torch, ix, qb, 100, args.steps, args.warmup, preselect=True)
+                res = (None, None, t["count"], t["n_match"])
+                rf = preselect_roofline(c, 512, res, t["stats"], t["scan_ms"])
+                points.append({"dtype": dt, "q": q, "qps": round(t["qps"], 1),
+                               "scan_ms": round(t["scan_ms"], 4),
+                               "search_ms_device": round(t["total_ms"], 4),
+                               "alg_gbs": rf["hbm_gbs"], "valu_tops": rf["valu_tops"],
+                               "frac_hbm": rf["hbm_frac"], "frac_alu": rf["alu_frac"],
+                               "bound": rf["bound"],
+                               "survivors_per_query": round(t["stats"].candidates / q, 1)})
+                log(json.dumps(points[-1]))
+                continue
             til = ix.autotune(qb.emb, qb, 100)
             t = timed_search(torch, ix, qb, 100, args.steps, args.warmup)
             st = t["stats"]
@@ -433,33 +485,79 @@ def bench_qsweep(args, torch):
         ix.close()
     line = {"metric": "scan roofline vs queries per pass", "config": {
         "workload": f"qsweep: {c.n:,} docs x {cfg.dim}-d, vocab {cfg.vocab}, K=100, "
-                    "batches of the first Q of 1,024 queries; BF16/FP8 with R=128",
+                    "batches of the first Q of 1,024 queries; BF16/FP8 with R=128; "
+                    "sign512 = 512-bit sign-code pre-selection, quantK = 200 K",
+        "n_docs": c.n}, "points": points, "data": "synthetic"}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def _cnf_rows(qb, a: int, b: int):
+    """The Cnf of queries [a, b) of a query batch (offsets rebased to 0)."""
+    from paper_2402_13435_amd import Cnf
+    co = qb.clause_off[a:b + 1]
+    lo = qb.literal_off[co[0]:co[-1] + 1]
+    return Cnf(co - co[0], lo - lo[0], qb.terms[lo[0]:lo[-1]])
+
+
+def bench_quantk(args, torch):
+    """Recall of the sign-code pre-selection against quantK (= factor x K)
+    and the code length, on the fp32 workload (1M x 128, 256 queries at
+    0.1%-50% selectivity, K=100): recall@100 against the exact oracle on a
+    stratified sample of the timed batch, QPS, survivors per query."""
+    import datagen
+    c, qb = datagen.workload("fp32")
+    k = 100
+    sample = stratified(qb, args.sample)
+    log(f"oracle on {len(sample)} queries")
+    o, res, _ = oracle_sample(c, qb, sample, lambda q: k)
+    points = []
+    for bits in (256, 512):
+        for factor in (5, 10, 20, 50, 100, 200):
+            r = run_form(torch, c, qb, k, "f32", args.steps, args.warmup, host=False,
+                         preselect=(bits, factor))
+            rep = precision_report(o, qb, res, r["res"][0], r["res"][1], r["res"][2],
+                                   lambda q: k)
+            points.append({"bits": bits, "factor": factor, "quant_k": factor * k,
+                           "recall_at_100": rep["recall"], "queries": rep["queries"],
+                           "qps": round(qb.n * args.steps / r["elapsed"], 1),
+                           "search_ms_device": round(float(np.mean(r["total_ms"])), 4),
+                           "scan_ms": round(float(np.mean(r["scan_ms"])), 4),
+                           "survivors_per_query": round(r["stats"].candidates / qb.n, 1)})
+            log(json.dumps(points[-1]))
+    line = {"metric": "sign-code pre-selection: recall@100 vs quantK", "config": {
+        "workload": f"quantk: {c.n:,} docs x {c.cfg.dim}-d FP32, vocab {c.cfg.vocab}, "
+                    f"{qb.n} CNF queries at 0.1%-50% selectivity, K={k}; codes drawn by "
+                    "datagen.sign_projection (bins of 2 over concatenated permutations)",
         "n_docs": c.n}, "points": points, "data": "synthetic"}
     print(json.dumps(line), flush=True)
     return 0
 
 
 def bench_serving(args, torch):
-    """Resident BF16 corpus, Poisson arrivals at fixed rates, continuous
-    batching over several workspaces, document inserts and deletes at 1% of
-    the corpus per minute in 100 ms batches; p50/p99 latency and QPS."""
+    """Resident BF16 corpus, open-loop Poisson arrivals at fixed fractions of
+    saturation, continuous batching by the library's request loop (fr_server:
+    a batch of everything pending whenever fewer than two batches are on the
+    device), document inserts and deletes at 1% of the corpus per minute in
+    100 ms batches; per level the achieved QPS and p50/p99 latency, measured
+    from each request's scheduled arrival to its completion."""
     import threading
     import datagen
     from paper_2402_13435_amd import Index
-    from paper_2402_13435_amd.serve import Server, latency_summary
+    from paper_2402_13435_amd.serve import Server, ResultRows, clock_ns
     cfg = datagen.CONFIGS["serving"]
     if args.n_docs:
         cfg = datagen.scaled(cfg, args.n_docs)
     log(f"generating the serving workload ({cfg.n_docs} docs)")
     c = datagen.corpus(cfg)
     qb = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms))
-    slots, bmax = 3, 256
+    inflight, bmax = 2, 256
     ix = Index(int(c.n * 1.02) + 1024, cfg.dim, cfg.vocab, 100, dtype="bf16", rescore_r=1024,
-               max_batch=bmax, n_workspaces=slots)
+               max_batch=bmax, n_workspaces=inflight)
     ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
     # saturation: back-to-back full batches
     sub = qb.subset(list(range(bmax)))
-    t = timed_search(torch, ix, sub, sub.k, 5, 2)
+    t = timed_search(torch, ix, sub, sub.k, 10, 3)
     sat = t["qps"]
     per_min = 0.01 * c.n
     upd_batch = max(2, int(per_min / 600))          # 100 ms batches
@@ -469,17 +567,18 @@ def bench_serving(args, torch):
     for frac in args.levels:
         rate = frac * sat
         n_req = int(min(args.max_requests, max(200, rate * args.level_s)))
-        plan.append((rate, n_req))
-    n_upd = sum(int(n / r / 0.1) + 20 for r, n in plan)
+        plan.append((frac, rate, n_req))
+    n_upd = sum(int(n / r / 0.1) + 20 for _, r, n in plan)
     log_live = np.asarray(c.ids[:: max(1, c.n // 100000)], dtype=np.uint32)
-    log(f"update log: {n_upd} batches of {upd_batch} documents")
+    log(f"saturation {sat:.0f} QPS; update log: {n_upd} batches of {upd_batch} documents")
     ups = datagen.update_log(cfg, log_live, n_upd, upd_batch)
     next_upd = [0]
     upd_errors = []
     levels = []
-    for rate, n_req in plan:
+    for frac, rate, n_req in plan:
         arr = datagen.arrivals(cfg, rate, n_req, level=len(levels))
-        srv = Server(ix, slots=slots, max_batch=bmax)
+        srv = Server(ix, max_inflight=inflight, max_batch=bmax)
+        rows = ResultRows(n_req, ix.k_max)
         stop = threading.Event()
         applied = [0]
 
@@ -497,32 +596,46 @@ def bench_serving(args, torch):
                 applied[0] += 1
 
         th = threading.Thread(target=updater, daemon=True)
-        futs = []
-        t0 = time.perf_counter()
         th.start()
-        for i in range(n_req):
-            now = time.perf_counter() - t0
-            if arr[i] > now:
-                time.sleep(arr[i] - now)
-            qi = i % qb.n
-            futs.append(srv.submit(qb.emb[qi], qb.cnf(qi), int(qb.k[qi])))
-        reps = [f.result(timeout=120) for f in futs]
-        wall = time.perf_counter() - t0
+        # open loop: every request whose scheduled arrival has passed is
+        # submitted at once, stamped with its scheduled arrival time
+        t_arr = (clock_ns() + 2_000_000 + arr * 1e9).astype(np.uint64)
+        i, last = 0, -1
+        while i < n_req:
+            j = int(np.searchsorted(t_arr, np.uint64(clock_ns()), side="right"))
+            if j <= i:
+                time.sleep(5e-5)
+                continue
+            while i < j:
+                a = i % qb.n
+                e = min(j, i + qb.n - a)
+                b = a + e - i
+                last = srv.submit_many(qb.emb[a:b], _cnf_rows(qb, a, b), qb.k[a:b],
+                                       t_arr[i:e], rows, i) + (e - i) - 1
+                i = e
+        srv.wait(last, timeout_s=120)
+        st = srv.stats()
         stop.set()
         th.join()
         srv.close()
-        s = latency_summary(reps)
-        levels.append({"offered_qps": round(rate, 1), "achieved_qps": round(n_req / wall, 1),
-                       "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
-                       "requests": n_req, "mean_batch": round(float(np.mean(srv.batches)), 1),
+        lat = (rows.done_ns.astype(np.int64) - t_arr.astype(np.int64)) * 1e-6
+        wall = float(rows.done_ns.max() - t_arr[0]) * 1e-9
+        levels.append({"load": frac, "offered_qps": round(rate, 1),
+                       "achieved_qps": round(n_req / wall, 1),
+                       "achieved_over_offered": round(n_req / wall / rate, 4),
+                       "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                       "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                       "requests": n_req, "mean_batch": round(st["mean_batch"], 1),
+                       "max_batch": st["max_batch_seen"],
+                       "failed": int(np.sum(rows.status != 0)),
                        "update_batches": applied[0]})
         log(json.dumps(levels[-1]))
     line = {"metric": "serving: p50/p99 latency and QPS under Poisson arrivals", "config": {
         "workload": f"serving: {c.n:,} docs x {cfg.dim}-d BF16 resident, vocab {cfg.vocab}, "
-                    f"K in {{10,100}}, updates 1%/min in 100 ms batches, {slots} workspaces, "
-                    f"batches <= {bmax}", "n_docs": c.n},
-        "saturation_qps": round(sat, 1), "levels": levels, "update_errors": upd_errors,
-        "data": "synthetic"}
+                    f"K in {{10,100}}, R=1024, updates 1%/min in 100 ms batches, "
+                    f"batches <= {bmax}, {inflight} in flight", "n_docs": c.n},
+        "saturation_qps": round(sat, 1), "saturation_search_ms": round(t["total_ms"], 3),
+        "levels": levels, "update_errors": upd_errors, "data": "synthetic"}
     ix.close()
     print(json.dumps(line), flush=True)
     return 0
@@ -537,7 +650,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--config", default="fp32",
-                    choices=["fp32", "precision", "batching", "serving", "qsweep"],
+                    choices=["fp32", "precision", "batching", "serving", "qsweep", "quantk"],
                     help="workload (default fp32: the benchmark line)")
     ap.add_argument("--n-docs", type=int, default=0, help="resize the corpus (non-default configs)")
     ap.add_argument("--q-sizes", default="1,8,32,64,128,256,512,1024",
@@ -545,7 +658,7 @@ def main() -> int:
     ap.add_argument("--sample", type=int, default=32, help="oracle-checked queries")
     ap.add_argument("--levels", type=float, nargs="*", default=[0.1, 0.3, 0.5, 0.7, 0.9])
     ap.add_argument("--level-s", type=float, default=10.0)
-    ap.add_argument("--max-requests", type=int, default=20000)
+    ap.add_argument("--max-requests", type=int, default=400000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run an elementwise kernel that reads and "
                          "writes 1 GiB (known traffic, to scale HBM counter readings)")
@@ -576,6 +689,8 @@ def main() -> int:
         return bench_qsweep(args, torch)
     if args.config == "serving":
         return bench_serving(args, torch)
+    if args.config == "quantk":
+        return bench_quantk(args, torch)
     t_start = time.perf_counter()
     log("generating the fp32 workload (1M docs x 128, 256 queries + a tuning batch)")
     c, qb = datagen.workload("fp32")
@@ -696,6 +811,26 @@ def main() -> int:
                 f["failed_queries"] = int(np.sum(r["res"][2] == 0xFFFFFFFF))
             f["r_tuning"] = tried
             forms[dt] = f
+        # sign-code pre-selection: 512-bit codes, quantK = 200 k survivors
+        # scored in FP32 (the paper's settings)
+        log("preselect form: 512-bit sign codes, quantK = 200 k")
+        r = run_form(torch, c, qb, k, "f32", args.steps, args.warmup, blocks=3, host=False,
+                     preselect=(512, 200))
+        f = {"qps": round(n_q * args.steps / r["elapsed"], 1),
+             "scan_ms": round(float(np.mean(r["scan_ms"])), 4),
+             "search_ms_device": round(float(np.mean(r["total_ms"])), 4),
+             "quant_bits": 512, "quant_k": 200 * k,
+             "survivors_per_query": round(r["stats"].candidates / n_q, 1),
+             "vs_f32_qps": round((n_q * args.steps / r["elapsed"]) / qps, 3),
+             "roofline": preselect_roofline(c, 512, r["res"], r["stats"],
+                                            float(np.mean(r["scan_ms"])))}
+        if oracle_res:
+            rep = precision_report(o, qb, oracle_res, r["res"][0], r["res"][1], r["res"][2],
+                                   lambda q: k)
+            f["recall_at_100"] = rep["recall"]
+            f["recall_queries"] = rep["queries"]
+            f["max_score_err"] = rep["max_score_err"]
+        forms["preselect512"] = f
         line["forms"] = forms
     if not args.no_c3:
         spent = time.perf_counter() - t_start

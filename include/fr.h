@@ -65,6 +65,8 @@ typedef enum {
                               call's fr_timings entry then has scan_ms == total_ms */
 #define FR_ASYNC       8u  /* fr_search: enqueue on `stream` and return even when `stream`
                               is NULL (then the null stream); needs FR_DEVICE_PTRS */
+#define FR_PRESELECT  16u  /* fr_search: sign-code coarse pre-selection before exact
+                              scoring (see fr_set_quantizer); not with FR_GRAPH */
 
 typedef struct {
   uint64_t capacity;       /* maximum live documents (slots); rounded up to 1024 */
@@ -84,6 +86,10 @@ typedef struct {
   uint32_t n_workspaces;   /* fr_search calls that may be in flight (0 -> 1) */
   uint32_t cand_cap;       /* candidate slots per query per pass (0 -> default) */
   int device;              /* HIP device ordinal */
+  uint32_t quant_bits;     /* sign-code bits per document for FR_PRESELECT searches:
+                              0 (none), 64, 128, 256 or 512 (the paper's choice) */
+  uint32_t quant_factor;   /* FR_PRESELECT keeps quantK = min(quant_factor * k[q], 65536)
+                              documents per query (0 -> 200, the paper's choice) */
 } fr_config;
 
 /* A batch of CNF predicates in CSR-of-CSR form (host memory):
@@ -155,8 +161,20 @@ fr_status fr_load_corpus(fr_index* ix, uint64_t n, const float* emb, const uint3
  * FR_ENOTFOUND; inserting an id that stays live -> FR_EDUPID; too many
  * live docs -> FR_ECAPACITY).  Freed slots are reused.  The update is
  * ordered after every search already issued on the index and before every
- * later one.  `out_epoch` (may be NULL) receives the new corpus epoch
- * (incremented once per successful load or update).  Synchronous. */
+ * later one, on the device: it is enqueued on the index's stream behind the
+ * searches in flight, later searches on other streams wait for it there, and
+ * the call returns without waiting for either (a later search captured into
+ * a caller's graph waits on the host instead; searches that a caller
+ * replays from its own graph are ordered by the caller).  The inputs are
+ * copied into the library's pinned staging before the call returns, so the
+ * caller may reuse them at once.  Only an update larger than one staging
+ * chunk (16,384 documents) waits on the host, for the previous chunk's
+ * copies.  A delete clears exactly the deleted document's term bits, from
+ * the term lists the library keeps on the host (a copy of every live
+ * document's list, compacted once half of it is stale).
+ * `out_epoch` (may be NULL) receives the new corpus epoch (incremented once
+ * per successful load or update).  A device error while enqueueing marks
+ * the index failed (FR_EDEVICE). */
 fr_status fr_update_docs(fr_index* ix, uint64_t n_del, const uint32_t* del_ids,
                          uint64_t n_ins, const uint32_t* ins_ids, const float* ins_emb,
                          const uint64_t* ins_term_off, const uint32_t* ins_terms,
@@ -225,6 +243,34 @@ fr_status fr_search_noalloc(fr_index* ix, uint32_t n_q, const float* queries,
                             float* out_scores, uint32_t* out_count, uint64_t* out_nmatch,
                             void* stream, uint32_t flags);
 
+/* Sign-code coarse pre-selection (Sec. 5.3, last paragraph; appendix
+ * "Optimizing System on GPU", Quantization): an OP+ORP-like code per
+ * document, of quant_bits bits.  Bit j of a code is set when the sum over
+ * bin j of sign * coordinate is positive, bin j being the table entries
+ * bin_off[j] .. bin_off[j+1] of (bin_dim, bin_sign); the paper builds the
+ * bins from a random permutation of the coordinates cut into equal parts,
+ * with a random sign per coordinate, and the caller draws them (the
+ * library's tests use several permutations with bins of two coordinates
+ * when quant_bits exceeds half the dimension).  Sums are taken in FP32 in
+ * table order from +0.
+ * An FR_PRESELECT search scores every predicate match by the number of code
+ * bits it shares with the query's code (the popcount of the complemented
+ * XOR of the words), keeps the quantK = min(quant_factor * k[q], 65536)
+ * best by (that score desc, id asc), scores only those in FP32 against the
+ * FP32 copy of the embeddings, and returns their top k[q] by (FP32 score
+ * desc, id asc), in the layout of fr_search.  out_nmatch still counts every
+ * match.  A query with more matches tied at its cut-off score than
+ * max(min(quant_factor * k_max, 65536), 16384) gets the failure marker of
+ * fr_search.
+ * bin_off: quant_bits + 1 entries (host), bin_off[0] = 0, non-decreasing,
+ * at most quant_bits x (dim rounded up to 64) entries in all; bin_dim: each
+ * < dim; bin_sign: each +1.0f or -1.0f.  Replaces the table and re-encodes
+ * every stored document from its FP32 copy; later loads and inserts are
+ * encoded as they are written.  Synchronous (waits for searches in flight).
+ * Errors: FR_EINVAL (index without quant_bits, malformed table), FR_EDEVICE. */
+fr_status fr_set_quantizer(fr_index* ix, const uint32_t* bin_off, const uint32_t* bin_dim,
+                           const float* bin_sign);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* fr_last_error(void);
 
@@ -243,6 +289,80 @@ fr_status fr_timings(fr_index* ix, uint32_t max, float* scan_ms, float* total_ms
 /* Current number of live documents, corpus epoch and slots in use (the
  * highest occupied slot + 1).  Any output may be NULL. */
 fr_status fr_info(fr_index* ix, uint64_t* n_live, uint64_t* epoch, uint64_t* n_slots);
+
+/* ---- serving ----------------------------------------------------------- */
+
+/* A request loop over one index (appendix, "Batch Inference": requests are
+ * bundled so that one scan of the corpus answers a whole batch; the batch
+ * size trades latency for throughput).  Requests are queued by
+ * fr_server_submit from any thread; a dispatcher thread forms a batch of
+ * everything pending (in submission order, up to max_batch queries and the
+ * index's clause and literal limits) whenever fewer than max_inflight
+ * batches are on the device, so the batch size follows the arrival rate,
+ * and enqueues it on the server's own stream (fr_search with device
+ * buffers the server owns); a completion thread copies each finished
+ * batch's rows to the caller's buffers.  Batches run and complete in
+ * submission order.  Updates go to the index directly (fr_update_docs);
+ * they are ordered between batches by the index. */
+typedef struct fr_server fr_server;
+
+typedef struct {
+  uint32_t max_batch;     /* queries per batch, 1..the index's max_batch (0 -> max_batch) */
+  uint32_t max_inflight;  /* batches on the device at once, 1..the index's n_workspaces
+                             (0 -> min(2, n_workspaces)); 2 keeps the device busy
+                             while the host forms the next batch */
+  uint32_t max_wait_us;   /* while no batch is on the device, wait up to this long after
+                             the oldest request's arrival for a fuller batch (0 -> never) */
+} fr_server_config;
+
+typedef struct {
+  uint64_t batches;         /* batches dispatched */
+  uint64_t queries;         /* requests dispatched */
+  uint64_t failed;          /* requests completed with a status other than FR_OK */
+  uint32_t max_batch_seen;  /* largest batch dispatched */
+  uint32_t pending;         /* requests waiting for a batch now */
+} fr_server_stats;
+
+/* Start a server on `ix` (which must outlive it).  Allocates its stream,
+ * events and max_inflight sets of device and pinned batch buffers, and
+ * starts its two threads.  Errors: FR_EINVAL, FR_ENOMEM, FR_EDEVICE. */
+fr_status fr_server_create(fr_index* ix, const fr_server_config* cfg, fr_server** out);
+
+/* Queue n requests: queries n x dim FP32 (host), their predicates (host,
+ * see fr_cnf_batch; cnf->n_queries == n), k (host, each 0..k_max), and
+ * t_arrival_ns (host, fr_clock_ns() times; NULL -> now), the times the
+ * requests count as arrived for max_wait_us.  All inputs are copied before
+ * the call returns.  The results go to caller memory that must stay valid
+ * until the requests complete: out_ids / out_scores n x k_max (rows as
+ * fr_search writes them), out_count and out_nmatch n entries, and, when not
+ * NULL, out_done_ns (n completion times, fr_clock_ns) and out_status (n
+ * fr_status values: FR_OK; FR_EUNSUPPORTED for a query marked failed,
+ * whose out_count is then 0xFFFFFFFF; or the error of a batch that could
+ * not be enqueued, whose rows are padding with count 0xFFFFFFFF).  Requests
+ * get consecutive tickets; `out_first_ticket` receives the first.  The whole
+ * call is validated first (K > k_max, a term >= vocab, a request with more
+ * clauses or literals than one search takes -> FR_EINVAL, nothing queued).
+ * Errors: FR_EINVAL (also after fr_server_destroy began). */
+fr_status fr_server_submit(fr_server* sv, uint32_t n, const float* queries,
+                           const fr_cnf_batch* cnf, const uint32_t* k,
+                           const uint64_t* t_arrival_ns, uint32_t* out_ids, float* out_scores,
+                           uint32_t* out_count, uint64_t* out_nmatch, uint64_t* out_done_ns,
+                           int32_t* out_status, uint64_t* out_first_ticket);
+
+/* Wait until every request with a ticket <= `ticket` has completed (its
+ * outputs written).  timeout_ms: 0 polls, 0xFFFFFFFF waits without limit.
+ * Errors: FR_EINVAL (ticket never issued), FR_EBUSY (timed out). */
+fr_status fr_server_wait(fr_server* sv, uint64_t ticket, uint32_t timeout_ms);
+
+/* Counters since fr_server_create. */
+fr_status fr_server_get_stats(fr_server* sv, fr_server_stats* out);
+
+/* Serve every request already queued, stop both threads and release the
+ * server's memory.  NULL is allowed. */
+fr_status fr_server_destroy(fr_server* sv);
+
+/* The clock of t_arrival_ns and out_done_ns: a monotonic clock in ns. */
+uint64_t fr_clock_ns(void);
 
 /* ---- testing and tuning entry points ---------------------------------- */
 
@@ -322,6 +442,10 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
 fr_status fr_tuning_choice(fr_index* ix, uint32_t n_q, const uint32_t* k,
                            uint32_t* out_query_blocks, uint32_t* out_waves,
                            uint32_t* out_groups, uint32_t* out_strategy, uint32_t* out_source);
+
+/* Sign codes of slots [slot0, slot0 + n) (host out, n x quant_bits / 64
+ * words, bit b of word w = code bit 64 w + b).  Waits for work in flight. */
+fr_status fr_debug_codes(fr_index* ix, uint64_t slot0, uint64_t n, uint64_t* out);
 
 /* Write the tuning table as JSON lines (one object per entry: arch, dtype,
  * dim, vocab, q_bucket, k_bucket, sel_bucket, query_blocks, waves,

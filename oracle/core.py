@@ -243,9 +243,9 @@ class OracleIndex:
     def search_rescored_one(self, q, cnf, k: int, r: int, storage: str) -> OracleResult:
         """Reduced-precision pipeline: approximate top-r by (approx desc, id
         asc), then exact rescoring of those r and top-k by (exact desc, id
-        asc).  This mirrors the paper's use of a cheap pre-selection that
-        "does not have to be very accurate" ahead of exact scoring (appendix,
-        "Quantization"), with the cut-off r playing the role of quantK."""
+        asc).  This mirrors the paper's use of a cheap, approximate
+        pre-selection ahead of exact scoring (appendix, "Quantization"), with
+        the cut-off r playing the role of quantK."""
         rows = self.match_rows(cnf)
         a = self.approx_scores(q, rows, storage)
         pre = np.lexsort((self.ids[rows], -a))[:min(int(r), len(rows))]

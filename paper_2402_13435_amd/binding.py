@@ -22,7 +22,7 @@ FR_ENOTFOUND, FR_EUNSUPPORTED, FR_EDEVICE, FR_EBUSY = -5, -6, -7, -8
 STATUS_NAMES = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_ECAPACITY",
                 -4: "FR_EDUPID", -5: "FR_ENOTFOUND", -6: "FR_EUNSUPPORTED",
                 -7: "FR_EDEVICE", -8: "FR_EBUSY"}
-FR_DEVICE_PTRS, FR_NOWAIT, FR_GRAPH, FR_ASYNC = 1, 2, 4, 8
+FR_DEVICE_PTRS, FR_NOWAIT, FR_GRAPH, FR_ASYNC, FR_PRESELECT = 1, 2, 4, 8, 16
 FR_STRAT_NO_SPECULATION, FR_STRAT_NO_REFRESH = 1, 2
 DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
 
@@ -39,7 +39,8 @@ class FrConfig(ctypes.Structure):
                 ("dtype", ctypes.c_int), ("max_batch", ctypes.c_uint32),
                 ("max_clauses", ctypes.c_uint32), ("max_literals", ctypes.c_uint32),
                 ("n_workspaces", ctypes.c_uint32), ("cand_cap", ctypes.c_uint32),
-                ("device", ctypes.c_int)]
+                ("device", ctypes.c_int), ("quant_bits", ctypes.c_uint32),
+                ("quant_factor", ctypes.c_uint32)]
 
 
 class FrCnfBatch(ctypes.Structure):
@@ -53,6 +54,17 @@ class FrStats(ctypes.Structure):
                 ("n_terms_batch", ctypes.c_uint64), ("alg_bytes", ctypes.c_double),
                 ("alg_flops", ctypes.c_double), ("ms_scan", ctypes.c_float),
                 ("ms_total", ctypes.c_float)]
+
+
+class FrServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
+                ("max_wait_us", ctypes.c_uint32)]
+
+
+class FrServerStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("queries", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("max_batch_seen", ctypes.c_uint32),
+                ("pending", ctypes.c_uint32)]
 
 
 class FrError(RuntimeError):
@@ -90,6 +102,16 @@ SYMBOLS = {
     "fr_tuning_choice": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _u32p, _u32p, _u32p, _u32p,
                                         _u32p]),
     "fr_tuning_load": (ctypes.c_int, [_vp, ctypes.c_char_p, _u32p]),
+    "fr_set_quantizer": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "fr_debug_codes": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, _vp]),
+    "fr_server_create": (ctypes.c_int, [_vp, ctypes.POINTER(FrServerConfig),
+                                        ctypes.POINTER(_vp)]),
+    "fr_server_submit": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.POINTER(FrCnfBatch),
+                                        _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64p]),
+    "fr_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint32]),
+    "fr_server_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(FrServerStats)]),
+    "fr_server_destroy": (ctypes.c_int, [_vp]),
+    "fr_clock_ns": (ctypes.c_uint64, []),
 }
 
 
@@ -201,16 +223,21 @@ class Index:
     def __init__(self, capacity: int, dim: int, vocab: int, k_max: int, dtype: str = "f32",
                  rescore_r: int = 0, rescore_min: int = 0, max_batch: int = 1024,
                  max_clauses: int = 0, max_literals: int = 0, n_workspaces: int = 1,
-                 cand_cap: int = 0, device: int = 0):
+                 cand_cap: int = 0, device: int = 0, quant_bits: int = 0,
+                 quant_factor: int = 0):
         self._h = None
         cfg = FrConfig(capacity, dim, vocab, k_max, rescore_r, rescore_min, DTYPES[dtype],
-                       max_batch, max_clauses, max_literals, n_workspaces, cand_cap, device)
+                       max_batch, max_clauses, max_literals, n_workspaces, cand_cap, device,
+                       quant_bits, quant_factor)
         h = _vp()
         _check(lib().fr_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self.dim, self.vocab, self.k_max, self.dtype = dim, vocab, k_max, dtype
         self.rescore_r = (rescore_r or 4096) if dtype != "f32" else 0
         self.max_batch = max_batch
+        self.n_workspaces = max(1, n_workspaces)
+        self.quant_bits = quant_bits
+        self.quant_factor = quant_factor or 200
 
     # ----------------------------------------------------------- lifecycle
     def close(self) -> None:
@@ -263,7 +290,8 @@ class Index:
 
     # --------------------------------------------------------------- search
     def search(self, queries, cnf, k, out: Optional[SearchResult] = None, stream=None,
-               nowait: bool = False, graph: bool = False) -> SearchResult:
+               nowait: bool = False, graph: bool = False,
+               preselect: bool = False) -> SearchResult:
         """Filtered top-K of a query batch.
 
         Host NumPy queries -> host NumPy results (synchronous).  Device
@@ -275,7 +303,8 @@ class Index:
         k = _host(np.broadcast_to(np.asarray(k, dtype=np.uint32), (n_q,)), np.uint32)
         dev = _is_dev(queries)
         flags = ((FR_DEVICE_PTRS if dev else 0) | (FR_NOWAIT if nowait else 0) |
-                 (FR_GRAPH if graph else 0) | (FR_ASYNC if dev and stream is not None else 0))
+                 (FR_GRAPH if graph else 0) | (FR_ASYNC if dev and stream is not None else 0) |
+                 (FR_PRESELECT if preselect else 0))
         if dev:
             if out is None:
                 import torch
@@ -311,6 +340,19 @@ class Index:
                                        _ptr(out.ids), _ptr(out.scores), _ptr(out.count),
                                        _ptr(out.n_match), getattr(stream, "cuda_stream", stream),
                                        flags))
+        return out
+
+    def set_quantizer(self, bin_off, bin_dim, bin_sign) -> None:
+        """fr_set_quantizer: the sign-code table (see datagen.sign_projection
+        for the tests' draws); re-encodes the stored corpus."""
+        bin_off = _host(bin_off, np.uint32)
+        bin_dim = _host(bin_dim, np.uint32)
+        bin_sign = _host(bin_sign, np.float32)
+        _check(lib().fr_set_quantizer(self._h, _ptr(bin_off), _ptr(bin_dim), _ptr(bin_sign)))
+
+    def debug_codes(self, slot0: int, n: int) -> np.ndarray:
+        out = np.zeros((n, max(1, self.quant_bits // 64)), np.uint64)
+        _check(lib().fr_debug_codes(self._h, slot0, n, _ptr(out)))
         return out
 
     def stats(self) -> FrStats:

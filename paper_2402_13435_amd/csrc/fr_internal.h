@@ -269,6 +269,107 @@ struct RescoreArgs {
 };
 
 
+// ---- sign-code pre-selection (fr_quant.hip) ----------------------------
+// Codes of n_bits (64, 128, 256 or 512) per row.  The corpus layout keeps
+// the words of 64 consecutive slots together: word w of slot s is at
+// codes[((s / 64) * W + w) * 64 + s % 64], W = n_bits / 64, so a wavefront
+// reads one word of 64 documents as 512 contiguous bytes.
+constexpr int kQuantQB = 32;        // queries per block of the code scans
+constexpr uint32_t kQuantAll = 1u;  // take every tie at the threshold
+constexpr uint32_t kQuantFail = 2u; // more ties at the threshold than the tie buffer
+constexpr uint32_t kQuantMaxK = 1u << 16;  // most survivors per query
+
+struct SignArgs {
+  const float* rows;       // FP32 rows, `ld` floats apart
+  uint32_t ld;
+  uint64_t n;              // rows
+  const uint32_t* n_dev;   // device row count (min with n), or null
+  const uint32_t* slots;   // corpus slot of each row, or null -> slot_base + i
+  uint64_t slot_base;
+  const uint32_t* bin_off; // [n_bits + 1]: bit j sums entries bin_off[j] .. bin_off[j+1]
+  const uint32_t* bin_dim; //   of (coordinate, sign)
+  const float* bin_sign;
+  uint32_t dim;            // coordinates a row holds (bin_dim < dim)
+  uint32_t n_bits;
+  uint64_t* codes;
+  int corpus_layout;       // 1: corpus layout (above); 0: [row][W]
+};
+
+struct QuantArgs {
+  const uint64_t* codes;   // corpus codes
+  const uint64_t* qcode;   // [q][W]
+  const uint64_t* mw;      // predicate masks [(group * 16 + word) * ppad + q]
+  uint32_t ppad;
+  uint32_t n_slices;       // 64-document slices scanned (16 per group)
+  uint32_t spb;            // slices per thread block
+  uint32_t max_q;          // grid size (queries)
+  const uint32_t* n_dev;   // device: queries in the batch
+  uint32_t n_bits;
+  uint32_t* hist;          // [q][n_bits + 1] matches per score (histogram pass)
+  const uint32_t* thr;     // collect pass: per-query threshold score
+  const uint32_t* flag;    //   kQuantAll / kQuantFail
+  uint32_t* cnt;           //   survivors per query
+  uint32_t* surv;          //   [q][scap] survivor slots
+  uint32_t scap;
+  uint32_t* ntie;          //   ties at the threshold per query
+  uint32_t* ties;          //   [q][tcap]
+  uint32_t tcap;
+};
+
+struct QuantSelectArgs {
+  uint32_t max_q;
+  const uint32_t* n_dev;
+  const uint32_t* k;
+  uint32_t factor;         // quantK = factor * k, at most scap
+  uint32_t n_bits;
+  const uint32_t* hist;
+  uint32_t* thr;
+  uint32_t* need;          // ties to take at the threshold
+  uint32_t* flag;
+  uint32_t* cnt;
+  uint32_t* ntie;
+  const uint32_t* ties;
+  uint32_t* surv;
+  uint32_t scap, tcap;
+  const uint32_t* slot_ids;
+  // state of the exact selection that follows (no bucket cut, no rerun)
+  uint32_t* tau;
+  float* hinvw;
+  uint32_t* tsafe;
+  uint32_t* ovf;
+};
+
+struct QuantDotArgs {
+  uint32_t max_q;
+  const uint32_t* n_dev;
+  const uint32_t* cnt;
+  const uint32_t* surv;
+  uint32_t scap;
+  uint32_t max_cnt;        // grid size: most survivors of any query of the batch
+  const float* master;     // [slot][dpad]
+  uint32_t dpad;
+  const float* qrows;      // [q][q_ld]
+  uint32_t q_ld;
+  uint32_t dim;
+  unsigned long long* key; // [q][scap]: FP32 score key << 32 | slot
+};
+
+// Codes of a.n rows.
+hipError_t launch_sign_codes(const SignArgs& a, hipStream_t s);
+// Histogram pass: per query, matches per code-agreement score.
+hipError_t launch_quant_hist(const QuantArgs& a, hipStream_t s);
+// Per query: the threshold score that keeps quantK survivors, and the ties
+// to take at it; resets the survivor and tie counters.
+hipError_t launch_quant_cut(const QuantSelectArgs& a, hipStream_t s);
+// Collect pass: survivors above the threshold (and every tie when all are
+// taken), ties at the threshold to their own buffer.
+hipError_t launch_quant_collect(const QuantArgs& a, hipStream_t s);
+// The `need` lowest-id ties join the survivors; a failed query gets a count
+// above scap (the exact selection then marks it failed).
+hipError_t launch_quant_ties(const QuantSelectArgs& a, hipStream_t s);
+// FP32 inner products of the survivors against the master rows.
+hipError_t launch_quant_dots(const QuantDotArgs& a, hipStream_t s);
+
 // Launchers (fr_kernels.hip).  Each returns the HIP error of the launch.
 hipError_t launch_tile_rows(const TileRowsArgs& a, hipStream_t s);
 hipError_t launch_terms(const TermArgs& a, hipStream_t s);
@@ -286,9 +387,6 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s);
 hipError_t launch_rescore(const RescoreArgs& a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
-// Clear every term bit of the given slots (documents being deleted).
-hipError_t launch_clear_slot_terms(const uint32_t* slots, uint64_t n, uint64_t* bits,
-                                   uint32_t vocab, hipStream_t s);
 // flag |= 1 if any of x[0..n) is not finite.
 hipError_t launch_check_finite(const float* x, uint64_t n, uint32_t* flag, hipStream_t s);
 // Device address of the no-allocation scratch (kScratchBytes) on `device`,

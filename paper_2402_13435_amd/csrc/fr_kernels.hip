@@ -32,6 +32,7 @@
 
 #include <mutex>
 
+#include "fr_device.h"
 #include "fr_internal.h"
 
 namespace fr {
@@ -40,21 +41,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-// ------------------------------------------------------------ order keys
-// Scores map to 32-bit keys whose unsigned order is the float order
-// (-0 and +0 share a key).  A candidate's 64-bit key appends the complement
-// of its id, so the unsigned order of keys is (score desc, id asc) when
-// sorted descending.
-__device__ __forceinline__ uint32_t fkey(float s) {
-  uint32_t u = __float_as_uint(s);
-  if (u == 0x80000000u) u = 0u;
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float key2f(uint32_t k) {
-  if (k <= kKeyNegInf) return -INFINITY;
-  const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
-  return __uint_as_float(u);
-}
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -99,20 +85,6 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, uint64_t n) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
-}
-
-// Every launcher refuses a null pointer the kernel would dereference, so a
-// host-side wiring mistake becomes an error status instead of a GPU fault.
-#define FR_REQUIRE(p) \
-  do {                \
-    if (!(p)) return hipErrorInvalidValue; \
-  } while (0)
-
-static inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 65535u * 4) {
-  uint64_t g = (n + block - 1) / block;
-  if (g < 1) g = 1;
-  if (g > cap) g = cap;
-  return (unsigned)g;
 }
 
 // --------------------------------------------------- no-allocation scratch
@@ -278,30 +250,6 @@ hipError_t launch_live(const LiveArgs& a, hipStream_t s) {
   FR_REQUIRE(a.live);
   if (a.set) FR_REQUIRE(a.ids);
   hipLaunchKernelGGL(k_live, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-// One thread per (slot, term): clear the slot's bit in the term's run.
-__global__ __launch_bounds__(256) void k_clear_slot_terms(const uint32_t* slots, uint64_t n,
-                                                          uint64_t* bits, uint32_t vocab) {
-  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i >= n * vocab) return;
-  const uint64_t slot = slots[i / vocab];
-  const uint64_t t = i % vocab;
-  const uint64_t g = slot / kGroup;
-  const unsigned long long bit = 1ull << (slot % 64);
-  unsigned long long* p =
-      (unsigned long long*)bits + (g * vocab + t) * kWords + (slot % kGroup) / 64;
-  if (*p & bit) atomicAnd(p, ~bit);
-}
-hipError_t launch_clear_slot_terms(const uint32_t* slots, uint64_t n, uint64_t* bits,
-                                   uint32_t vocab, hipStream_t s) {
-  const uint64_t total = n * vocab;
-  if (!total) return hipSuccess;
-  FR_REQUIRE(slots);
-  FR_REQUIRE(bits);
-  hipLaunchKernelGGL(k_clear_slot_terms, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     slots, n, bits, vocab);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "fr.h"
+#include "fr_host.h"
 #include "fr_internal.h"
 
 using namespace fr;
@@ -125,6 +126,18 @@ struct Workspace {
   uint32_t* h_cnt = nullptr;
   uint32_t* h_selcnt = nullptr;
   uint32_t* h_desc_out = nullptr;  // device descriptor after the call ([2] = rerun list)
+  // sign-code pre-selection (indexes with sign codes)
+  uint64_t* qcode = nullptr;   // [q][W] query codes
+  uint32_t* qhist = nullptr;   // [q][bits + 1] matches per code score
+  uint32_t* qthr = nullptr;
+  uint32_t* qneed = nullptr;
+  uint32_t* qflag = nullptr;
+  uint32_t* ntie = nullptr;
+  uint32_t* surv = nullptr;    // [q][scap]
+  uint32_t* ties = nullptr;    // [q][tcap]
+  unsigned long long* qkey = nullptr;   // [q][scap]
+  bool last_preselect = false;
+  uint64_t last_survivors = 0;
   hipEvent_t done = nullptr, e_scan0 = nullptr, e_scan1 = nullptr, e_end = nullptr;
   // timing ring: scan start / scan end / end of the search, per recent call
   static constexpr int kRing = 64;
@@ -149,6 +162,15 @@ struct fr_index {
   uint32_t rmax = 0;       // per-query selection buffer (max of k_max and R)
   uint32_t r = 0, r_min = 0;
   uint32_t cand_cap = 0;
+  // sign codes: bits per document (0: none), quantK = factor * k (at most
+  // scap), tie buffer per query, the corpus codes and the encoding table
+  uint32_t qbits = 0, qfactor = 0, scap = 0, tcap = 0;
+  uint64_t* codes = nullptr;
+  uint32_t* d_bin_off = nullptr;
+  uint32_t* d_bin_dim = nullptr;
+  float* d_bin_sign = nullptr;
+  uint64_t bin_cap = 0;     // table entries reserved
+  bool quant_set = false;   // fr_set_quantizer was called
   uint32_t qmax = 0, cmax = 0, lmax = 0;
   uint32_t seed_groups = 0;   // corpus groups sampled for starting thresholds
   int n_cu = 0, n_wg = 0;
@@ -184,6 +206,29 @@ struct fr_index {
   uint32_t* d_ids = nullptr;
   uint32_t* d_slots = nullptr;
   uint32_t* h_flag = nullptr;
+  // update staging: device buffers and their pinned host twins for one
+  // chunk of an update (inserted rows, ids, term CSR, slots; deleted slots
+  // and their term CSR), so that an update is enqueued without waiting
+  uint64_t ustage_rows = 0, ustage_terms = 0;
+  float* d_urows = nullptr;
+  uint64_t* d_uoff = nullptr;
+  uint32_t *d_uterms = nullptr, *d_uids = nullptr, *d_uslots = nullptr;
+  uint32_t *d_dslots = nullptr, *d_dterms = nullptr;
+  uint64_t* d_doff = nullptr;
+  float* h_urows = nullptr;
+  uint64_t* h_uoff = nullptr;
+  uint32_t *h_uterms = nullptr, *h_uids = nullptr, *h_uslots = nullptr;
+  uint32_t *h_dslots = nullptr, *h_dterms = nullptr;
+  uint64_t* h_doff = nullptr;
+  hipEvent_t ustage_free = nullptr;   // the staging's last copies are done
+  hipEvent_t upd_done = nullptr;      // the last update's device work is done
+  bool ustage_pending = false, upd_pending = false;
+  // host copy of every slot's term list (so a delete clears exactly the
+  // document's term bits): slot s holds t_arena[t_off[s] .. + t_len[s])
+  std::vector<uint32_t> t_arena;
+  std::vector<uint64_t> t_off;
+  std::vector<uint32_t> t_len;
+  uint64_t t_garbage = 0;
   // host mirror of the slot store
   std::unordered_map<uint32_t, uint32_t> id2slot;
   std::vector<uint32_t> slot_id;
@@ -203,7 +248,8 @@ struct fr_index {
   uint32_t* na_h_in = nullptr;
   uint32_t* na_h_count = nullptr;
   hipEvent_t na_copied = nullptr;
-  bool na_pending = false;
+  hipEvent_t na_done = nullptr;   // end of the last scratch-array search
+  bool na_pending = false, na_inflight = false;
   std::mutex mu;
 };
 
@@ -268,6 +314,17 @@ size_t layout_workspace(const fr_index* ix, Workspace& w, uint8_t* base, uint32_
   carve(&w.mw, base, off, (size_t)std::max<uint64_t>(n_groups, 1) * kWords * w.ppad);
   carve(&w.sel_key, base, off, (size_t)qm * ix->rmax);
   carve(&w.sel_slot, base, off, (size_t)qm * ix->rmax);
+  if (outputs && ix->qbits) {
+    carve(&w.qcode, base, off, (size_t)qm * (ix->qbits / 64));
+    carve(&w.qhist, base, off, (size_t)qm * (ix->qbits + 1));
+    carve(&w.qthr, base, off, qm);
+    carve(&w.qneed, base, off, qm);
+    carve(&w.qflag, base, off, qm);
+    carve(&w.ntie, base, off, qm);
+    carve(&w.surv, base, off, (size_t)qm * ix->scap);
+    carve(&w.ties, base, off, (size_t)qm * ix->tcap);
+    carve(&w.qkey, base, off, (size_t)qm * ix->scap);
+  }
   if (outputs) {
     carve(&w.out_ids, base, off, (size_t)qm * ix->cfg.k_max);
     carve(&w.out_scores, base, off, (size_t)qm * ix->cfg.k_max);
@@ -291,6 +348,27 @@ void layout_host_inputs(Workspace& w, uint32_t* h_in) {
 
 namespace {
 
+// Sign codes of n FP32 rows (`ld` floats apart) into their corpus slots,
+// once the index has an encoding table.
+hipError_t encode_rows(fr_index* ix, const float* rows, uint32_t ld, uint64_t n,
+                       const uint32_t* slots, uint64_t slot_base) {
+  if (!ix->quant_set || !n) return hipSuccess;
+  SignArgs sa{};
+  sa.rows = rows;
+  sa.ld = ld;
+  sa.n = n;
+  sa.slots = slots;
+  sa.slot_base = slot_base;
+  sa.bin_off = ix->d_bin_off;
+  sa.bin_dim = ix->d_bin_dim;
+  sa.bin_sign = ix->d_bin_sign;
+  sa.dim = ix->dim;
+  sa.n_bits = ix->qbits;
+  sa.codes = ix->codes;
+  sa.corpus_layout = 1;
+  return launch_sign_codes(sa, ix->stream);
+}
+
 fr_status wait_all(fr_index* ix) {
   for (auto& w : ix->ws) {
     if (w.in_flight) {
@@ -298,8 +376,163 @@ fr_status wait_all(fr_index* ix) {
       w.in_flight = false;
     }
   }
+  if (ix->na_inflight) {
+    FR_HIP(hipEventSynchronize(ix->na_done));
+    ix->na_inflight = false;
+  }
   FR_HIP(hipStreamSynchronize(ix->stream));
+  ix->upd_pending = false;
+  ix->ustage_pending = false;
   return FR_OK;
+}
+
+// Make the index stream wait (on the device) for every search still in
+// flight: the workspaces' searches and the scratch-array search.
+fr_status order_after_searches(fr_index* ix) {
+  for (auto& w : ix->ws) {
+    if (!w.in_flight) continue;
+    if (hipEventQuery(w.done) == hipSuccess) w.in_flight = false;
+    else FR_HIP(hipStreamWaitEvent(ix->stream, w.done, 0));
+  }
+  if (ix->na_inflight) {
+    if (hipEventQuery(ix->na_done) == hipSuccess) ix->na_inflight = false;
+    else FR_HIP(hipStreamWaitEvent(ix->stream, ix->na_done, 0));
+  }
+  return FR_OK;
+}
+
+// A search on stream s sees every update issued before it: s waits on the
+// device for the last update (or, while s is being captured into a graph,
+// the host waits, so that no outside event enters the capture).
+fr_status order_after_update(fr_index* ix, hipStream_t s) {
+  if (!ix->upd_pending) return FR_OK;
+  if (hipEventQuery(ix->upd_done) == hipSuccess) {
+    ix->upd_pending = false;
+    return FR_OK;
+  }
+  if (s == ix->stream) return FR_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  FR_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) {
+    FR_HIP(hipEventSynchronize(ix->upd_done));
+    ix->upd_pending = false;
+    return FR_OK;
+  }
+  FR_HIP(hipStreamWaitEvent(s, ix->upd_done, 0));
+  return FR_OK;
+}
+
+// The pinned update staging is refilled only once its last copies ran.
+fr_status stage_wait(fr_index* ix) {
+  if (ix->ustage_pending) {
+    FR_HIP(hipEventSynchronize(ix->ustage_free));
+    ix->ustage_pending = false;
+  }
+  return FR_OK;
+}
+
+// A document's term list as staged: as given, or, if longer than the
+// staging holds, its distinct terms (at most the vocabulary, which fits);
+// setting or clearing a bit twice is the same as once.
+const uint32_t* doc_terms(const fr_index* ix, const uint32_t* t, uint64_t* len,
+                          std::vector<uint32_t>& tmp) {
+  if (*len <= ix->ustage_terms) return t;
+  tmp.assign(t, t + *len);
+  std::sort(tmp.begin(), tmp.end());
+  tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+  *len = tmp.size();
+  return tmp.data();
+}
+
+// Staged deletes h_dslots[0, m) with their term lists (h_doff, h_dterms):
+// copy, clear live bits and slot ids, clear the listed term bits.
+fr_status enqueue_deletes(fr_index* ix, uint64_t m, uint64_t nt) {
+  if (!m) return FR_OK;
+  FR_HIP(hipMemcpyAsync(ix->d_dslots, ix->h_dslots, m * 4, hipMemcpyHostToDevice, ix->stream));
+  FR_HIP(hipMemcpyAsync(ix->d_doff, ix->h_doff, (m + 1) * 8, hipMemcpyHostToDevice, ix->stream));
+  if (nt)
+    FR_HIP(hipMemcpyAsync(ix->d_dterms, ix->h_dterms, nt * 4, hipMemcpyHostToDevice, ix->stream));
+  FR_HIP(hipEventRecord(ix->ustage_free, ix->stream));
+  ix->ustage_pending = true;
+  LiveArgs la{};
+  la.slots = ix->d_dslots;
+  la.n = m;
+  la.slot_ids = ix->slot_ids;
+  la.live = ix->live;
+  la.set = 0;
+  FR_HIP(launch_live(la, ix->stream));
+  TermArgs tm{};
+  tm.off = ix->d_doff;
+  tm.terms = ix->d_dterms;
+  tm.slots = ix->d_dslots;
+  tm.n = m;
+  tm.bits = ix->bits;
+  tm.vocab = ix->cfg.vocab;
+  tm.set = 0;
+  FR_HIP(launch_terms(tm, ix->stream));
+  return FR_OK;
+}
+
+// Staged inserts (h_urows, h_uids, h_uslots, h_uoff, h_uterms) of m rows:
+// copy, tile the rows into their slots, set term bits, ids and live bits.
+fr_status enqueue_inserts(fr_index* ix, uint64_t m, uint64_t nt) {
+  if (!m) return FR_OK;
+  FR_HIP(hipMemcpyAsync(ix->d_urows, ix->h_urows, m * ix->dim * 4, hipMemcpyHostToDevice,
+                        ix->stream));
+  FR_HIP(hipMemcpyAsync(ix->d_uids, ix->h_uids, m * 4, hipMemcpyHostToDevice, ix->stream));
+  FR_HIP(hipMemcpyAsync(ix->d_uslots, ix->h_uslots, m * 4, hipMemcpyHostToDevice, ix->stream));
+  FR_HIP(hipMemcpyAsync(ix->d_uoff, ix->h_uoff, (m + 1) * 8, hipMemcpyHostToDevice, ix->stream));
+  if (nt)
+    FR_HIP(hipMemcpyAsync(ix->d_uterms, ix->h_uterms, nt * 4, hipMemcpyHostToDevice, ix->stream));
+  FR_HIP(hipEventRecord(ix->ustage_free, ix->stream));
+  ix->ustage_pending = true;
+  TileRowsArgs ta{};
+  ta.rows = ix->d_urows;
+  ta.n = m;
+  ta.dim = ix->dim;
+  ta.dpad = ix->dpad;
+  ta.dt = ix->dt;
+  ta.slots = ix->d_uslots;
+  ta.tiles = ix->tiles;
+  ta.scale = ix->xscale;
+  ta.master = ix->master;
+  ta.norm_max = ix->norm_max;
+  FR_HIP(launch_tile_rows(ta, ix->stream));
+  FR_HIP(encode_rows(ix, ix->d_urows, ix->dim, m, ix->d_uslots, 0));
+  TermArgs tm{};
+  tm.off = ix->d_uoff;
+  tm.terms = ix->d_uterms;
+  tm.slots = ix->d_uslots;
+  tm.n = m;
+  tm.bits = ix->bits;
+  tm.vocab = ix->cfg.vocab;
+  tm.set = 1;
+  FR_HIP(launch_terms(tm, ix->stream));
+  LiveArgs la{};
+  la.slots = ix->d_uslots;
+  la.n = m;
+  la.ids = ix->d_uids;
+  la.slot_ids = ix->slot_ids;
+  la.live = ix->live;
+  la.set = 1;
+  FR_HIP(launch_live(la, ix->stream));
+  return FR_OK;
+}
+
+// Rewrite the host term store over live slots once half of it is garbage.
+void compact_terms(fr_index* ix) {
+  if (ix->t_garbage < (1u << 20) || ix->t_garbage * 2 < ix->t_arena.size()) return;
+  std::vector<uint32_t> a;
+  const uint64_t live = ix->t_arena.size() - ix->t_garbage;
+  a.reserve(live + live / 4 + (1u << 22));
+  for (uint64_t sl = 0; sl < ix->hwm; ++sl) {
+    const uint32_t len = ix->t_len[sl];
+    const uint64_t o = ix->t_off[sl];
+    ix->t_off[sl] = a.size();
+    a.insert(a.end(), ix->t_arena.begin() + o, ix->t_arena.begin() + o + len);
+  }
+  ix->t_arena.swap(a);
+  ix->t_garbage = 0;
 }
 
 fr_status check_terms(const fr_index* ix, uint64_t n, const uint64_t* off, const uint32_t* terms) {
@@ -373,6 +606,7 @@ fr_status write_docs(fr_index* ix, uint64_t n, const float* emb, const uint32_t*
     ta.master = ix->master;
     ta.norm_max = ix->norm_max;
     FR_HIP(launch_tile_rows(ta, ix->stream));
+    FR_HIP(encode_rows(ix, rows, ix->dim, m, ta.slots, ta.slot_base));
     TermArgs tm{};
     tm.off = ix->d_off;
     tm.terms = ix->d_tl;
@@ -698,6 +932,147 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
   return FR_OK;
 }
 
+// Sign-code pre-selection search (FR_PRESELECT): query prep and masks as for
+// a plain search, query codes, the histogram pass, the per-query cut, the
+// collect pass, the lowest-id ties, FP32 scores of the survivors, and the
+// exact selection of their top K.  `max_qk` is the batch's largest quantK.
+fr_status enqueue_preselect(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_groups,
+                            uint32_t max_qk, bool timing, const float* qsrc, uint32_t* o_ids,
+                            float* o_scores, uint32_t* o_count, unsigned long long* o_nm) {
+  TileRowsArgs ta{};
+  const bool in_place = qsrc != w.qrow;
+  ta.rows = qsrc;
+  ta.n = w.qcap;
+  ta.n_dev = w.desc;
+  ta.dim = in_place ? ix->dim : ix->dpad;
+  ta.dpad = ix->dpad;
+  ta.dt = ix->dt;
+  ta.tiles = w.qtiles;
+  ta.scale = w.qscale;
+  ta.norm = w.qnorm;
+  FR_HIP(launch_query_prep(ta, prep_args(ix, w), s));
+  const uint32_t q_ld = in_place ? ix->dim : ix->dpad;
+  SignArgs qa{};
+  qa.rows = qsrc;
+  qa.ld = q_ld;
+  qa.n = w.qcap;
+  qa.n_dev = w.desc;
+  qa.bin_off = ix->d_bin_off;
+  qa.bin_dim = ix->d_bin_dim;
+  qa.bin_sign = ix->d_bin_sign;
+  qa.dim = ix->dim;
+  qa.n_bits = ix->qbits;
+  qa.codes = w.qcode;
+  FR_HIP(launch_sign_codes(qa, s));
+  const MaskWordArgs ma = mask_args(ix, w, n_groups);
+  FR_HIP(launch_mask_words(ma, s));
+  FR_HIP(launch_fill_u32(w.qhist, 0u, (uint64_t)w.qcap * (ix->qbits + 1), s));
+
+  QuantArgs qs{};
+  qs.codes = ix->codes;
+  qs.qcode = w.qcode;
+  qs.mw = w.mw;
+  qs.ppad = ma.ppad;
+  qs.n_slices = n_groups * (uint32_t)kWords;
+  qs.max_q = w.qcap;
+  qs.n_dev = w.desc;
+  qs.n_bits = ix->qbits;
+  // about four blocks per compute unit over the batch's query blocks
+  const uint32_t qblocks = (w.qcap + kQuantQB - 1) / kQuantQB;
+  const uint32_t xblocks = std::max<uint32_t>(1, (uint32_t)(4 * ix->n_cu) / qblocks);
+  qs.spb = std::max<uint32_t>(4, round_up((qs.n_slices + xblocks - 1) / xblocks, 4));
+  qs.hist = w.qhist;
+  qs.thr = w.qthr;
+  qs.flag = w.qflag;
+  qs.cnt = w.cnt;
+  qs.surv = w.surv;
+  qs.scap = ix->scap;
+  qs.ntie = w.ntie;
+  qs.ties = w.ties;
+  qs.tcap = ix->tcap;
+  if (timing) FR_HIP(hipEventRecord(w.e_scan0, s));
+  FR_HIP(launch_quant_hist(qs, s));
+
+  QuantSelectArgs qc{};
+  qc.max_q = w.qcap;
+  qc.n_dev = w.desc;
+  qc.k = w.k;
+  qc.factor = ix->qfactor;
+  qc.n_bits = ix->qbits;
+  qc.hist = w.qhist;
+  qc.thr = w.qthr;
+  qc.need = w.qneed;
+  qc.flag = w.qflag;
+  qc.cnt = w.cnt;
+  qc.ntie = w.ntie;
+  qc.ties = w.ties;
+  qc.surv = w.surv;
+  qc.scap = ix->scap;
+  qc.tcap = ix->tcap;
+  qc.slot_ids = ix->slot_ids;
+  qc.tau = w.tau;
+  qc.hinvw = w.hinvw;
+  qc.tsafe = w.tsafe;
+  qc.ovf = w.ovf;
+  FR_HIP(launch_quant_cut(qc, s));
+  FR_HIP(launch_quant_collect(qs, s));
+  if (timing) FR_HIP(hipEventRecord(w.e_scan1, s));
+  FR_HIP(launch_quant_ties(qc, s));
+
+  QuantDotArgs qd{};
+  qd.max_q = w.qcap;
+  qd.n_dev = w.desc;
+  qd.cnt = w.cnt;
+  qd.surv = w.surv;
+  qd.scap = ix->scap;
+  qd.max_cnt = max_qk;
+  qd.master = ix->master;
+  qd.dpad = ix->dpad;
+  qd.qrows = qsrc;
+  qd.q_ld = q_ld;
+  qd.dim = ix->dim;
+  qd.key = w.qkey;
+  FR_HIP(launch_quant_dots(qd, s));
+
+  SelectArgs se{};
+  se.qlist = w.qlist;
+  se.n_list = w.desc + 1;
+  se.max_list = w.qcap;
+  se.final_pass = 1;
+  se.kp = w.k;
+  se.tau = w.tau;
+  se.cnt = w.cnt;
+  se.smax = w.smax;
+  se.hist = w.hist;
+  se.hlo = w.hlo;
+  se.hinvw = w.hinvw;
+  se.qlist2 = w.qlist2;
+  se.n_list2 = w.desc + 2;
+  se.work = w.work;
+  se.qnorm = w.qnorm;
+  se.norm_max = ix->norm_max;
+  se.cand_key = w.qkey;
+  se.slot_ids = ix->slot_ids;
+  se.cap = ix->scap;
+  se.sel_key = w.sel_key;
+  se.sel_slot = w.sel_slot;
+  se.sel_cnt = w.sel_cnt;
+  se.rmax = ix->rmax;
+  se.ovf = w.ovf;
+  se.tsafe = w.tsafe;
+  se.write_out = 1;
+  se.k = w.k;
+  se.k_max = ix->cfg.k_max;
+  se.out_ids = o_ids;
+  se.out_scores = o_scores;
+  se.out_count = o_count;
+  se.nmatch = w.nmatch;
+  se.out_nmatch = o_nm;
+  FR_HIP(launch_select(se, s));
+  if (timing) FR_HIP(hipEventRecord(w.e_end, s));
+  return FR_OK;
+}
+
 // Pick the timing-ring slot of a call and remember it in the history.
 void ring_slot(fr_index* ix, Workspace& w) {
   const int slot = (int)(w.n_calls % Workspace::kRing);
@@ -789,6 +1164,26 @@ Workspace* acquire_ws(fr_index* ix, bool nowait, fr_status* st) {
 
 }  // namespace
 
+namespace fr {
+
+fr_status set_error(fr_status s, const std::string& msg) { return fail(s, msg); }
+
+fr_status index_shape(fr_index* ix, IndexShape* out) {
+  if (!ix || !out) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  out->dim = ix->dim;
+  out->vocab = ix->cfg.vocab;
+  out->k_max = ix->cfg.k_max;
+  out->max_batch = ix->qmax;
+  out->max_clauses = ix->cmax;
+  out->max_literals = ix->lmax;
+  out->n_workspaces = (uint32_t)ix->ws.size();
+  out->device = ix->cfg.device;
+  return FR_OK;
+}
+
+}  // namespace fr
+
 extern "C" {
 
 const char* fr_last_error(void) { return g_err.c_str(); }
@@ -831,6 +1226,15 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   if (ix->cand_cap < ix->rmax) return fail(FR_EINVAL, "cand_cap must be >= the selection size");
   if (!scan_supported(ix->dt, ix->dpad, 1, 4))
     return fail(FR_EUNSUPPORTED, "no scan kernel for this dtype/dim");
+  ix->qbits = cfg->quant_bits;
+  if (ix->qbits && ix->qbits != 64 && ix->qbits != 128 && ix->qbits != 256 && ix->qbits != 512)
+    return fail(FR_EINVAL, "quant_bits must be 0, 64, 128, 256 or 512");
+  ix->qfactor = cfg->quant_factor ? cfg->quant_factor : 200;
+  if (ix->qbits) {
+    ix->scap = (uint32_t)std::min<uint64_t>((uint64_t)ix->qfactor * cfg->k_max, kQuantMaxK);
+    ix->tcap = std::max<uint32_t>(ix->scap, 16384);
+    ix->bin_cap = (uint64_t)ix->qbits * ix->dpad;
+  }
   std::vector<void*>& D = ix->dev_owned;
   std::vector<void*>& H = ix->host_owned;
   auto cleanup = [&]() {
@@ -865,7 +1269,13 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   const size_t tb = tile_bytes(ix->dt, ix->dpad);
   FR_ALLOC(dalloc(&ix->tiles, cap / kTile * tb, D));
   if (ix->dt == kFP8) FR_ALLOC(dalloc(&ix->xscale, cap, D));
-  if (ix->dt != kF32) FR_ALLOC(dalloc(&ix->master, cap * ix->dpad, D));
+  if (ix->dt != kF32 || ix->qbits) FR_ALLOC(dalloc(&ix->master, cap * ix->dpad, D));
+  if (ix->qbits) {
+    FR_ALLOC(dalloc(&ix->codes, cap * (ix->qbits / 64), D));
+    FR_ALLOC(dalloc(&ix->d_bin_off, ix->qbits + 1, D));
+    FR_ALLOC(dalloc(&ix->d_bin_dim, ix->bin_cap, D));
+    FR_ALLOC(dalloc(&ix->d_bin_sign, ix->bin_cap, D));
+  }
   FR_ALLOC(dalloc(&ix->slot_ids, cap, D));
   FR_ALLOC(dalloc(&ix->live, cap / 64, D));
   FR_ALLOC(dalloc(&ix->bits, cap / kGroup * (uint64_t)cfg->vocab * kWords, D));
@@ -879,6 +1289,30 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   FR_ALLOC(dalloc(&ix->d_ids, ix->stage_rows, D));
   FR_ALLOC(dalloc(&ix->d_slots, ix->stage_rows, D));
   FR_ALLOC(halloc(&ix->h_flag, 1, H));
+  ix->ustage_rows = std::min<uint64_t>(cap, 1u << 14);
+  // any one document fits: its distinct terms number at most the vocabulary
+  ix->ustage_terms = std::max<uint64_t>(ix->ustage_rows * 64, cfg->vocab);
+  FR_ALLOC(dalloc(&ix->d_urows, ix->ustage_rows * ix->dim, D));
+  FR_ALLOC(dalloc(&ix->d_uoff, ix->ustage_rows + 1, D));
+  FR_ALLOC(dalloc(&ix->d_uterms, ix->ustage_terms, D));
+  FR_ALLOC(dalloc(&ix->d_uids, ix->ustage_rows, D));
+  FR_ALLOC(dalloc(&ix->d_uslots, ix->ustage_rows, D));
+  FR_ALLOC(dalloc(&ix->d_dslots, ix->ustage_rows, D));
+  FR_ALLOC(dalloc(&ix->d_doff, ix->ustage_rows + 1, D));
+  FR_ALLOC(dalloc(&ix->d_dterms, ix->ustage_terms, D));
+  FR_ALLOC(halloc(&ix->h_urows, ix->ustage_rows * ix->dim, H));
+  FR_ALLOC(halloc(&ix->h_uoff, ix->ustage_rows + 1, H));
+  FR_ALLOC(halloc(&ix->h_uterms, ix->ustage_terms, H));
+  FR_ALLOC(halloc(&ix->h_uids, ix->ustage_rows, H));
+  FR_ALLOC(halloc(&ix->h_uslots, ix->ustage_rows, H));
+  FR_ALLOC(halloc(&ix->h_dslots, ix->ustage_rows, H));
+  FR_ALLOC(halloc(&ix->h_doff, ix->ustage_rows + 1, H));
+  FR_ALLOC(halloc(&ix->h_dterms, ix->ustage_terms, H));
+  if (hipEventCreateWithFlags(&ix->ustage_free, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ix->upd_done, hipEventDisableTiming) != hipSuccess) {
+    cleanup();
+    return fail(FR_EDEVICE, "hipEventCreate failed");
+  }
 
   const uint32_t nws = cfg->n_workspaces ? cfg->n_workspaces : 1;
   ix->ws.resize(nws);
@@ -923,7 +1357,8 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   }
   FR_ALLOC(halloc(&ix->na_h_in, n_in, H));
   FR_ALLOC(halloc(&ix->na_h_count, qm, H));
-  if (hipEventCreateWithFlags(&ix->na_copied, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&ix->na_copied, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ix->na_done, hipEventDisableTiming) != hipSuccess) {
     cleanup();
     return fail(FR_EDEVICE, "hipEventCreate failed");
   }
@@ -942,6 +1377,8 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   }
   FR_HIP(hipStreamSynchronize(ix->stream));
   ix->slot_id.assign(cap, 0xFFFFFFFFu);
+  ix->t_off.assign(cap, 0);
+  ix->t_len.assign(cap, 0);
   *out = holder.release();
   return FR_OK;
 }
@@ -967,6 +1404,11 @@ fr_status fr_destroy(fr_index* ix) {
       (void)hipEventSynchronize(ix->na_copied);
       (void)hipEventDestroy(ix->na_copied);
     }
+    for (hipEvent_t e : {ix->na_done, ix->ustage_free, ix->upd_done})
+      if (e) {
+        (void)hipEventSynchronize(e);
+        (void)hipEventDestroy(e);
+      }
     if (ix->stream) {
       (void)hipStreamSynchronize(ix->stream);
       (void)hipStreamDestroy(ix->stream);
@@ -1024,6 +1466,20 @@ fr_status fr_load_corpus(fr_index* ix, uint64_t n, const float* emb, const uint3
   }
   ix->id2slot.swap(m);
   for (uint64_t i = 0; i < n; ++i) ix->slot_id[i] = hid[i];
+  // with headroom, so that inserts append without moving the arena (a
+  // move copies every list while the index is locked)
+  {
+    const uint64_t used = n ? term_off[n] - term_off[0] : 0;
+    std::vector<uint32_t>().swap(ix->t_arena);
+    ix->t_arena.reserve(used + used / 4 + (1u << 22));
+    ix->t_arena.assign(n ? terms + term_off[0] : terms, n ? terms + term_off[n] : terms);
+  }
+  std::fill(ix->t_len.begin(), ix->t_len.end(), 0u);
+  for (uint64_t i = 0; i < n; ++i) {
+    ix->t_off[i] = term_off[i] - term_off[0];
+    ix->t_len[i] = (uint32_t)(term_off[i + 1] - term_off[i]);
+  }
+  ix->t_garbage = 0;
   ix->hwm = n;
   ix->n_live = n;
   ix->epoch += 1;
@@ -1067,26 +1523,42 @@ fr_status fr_update_docs(fr_index* ix, uint64_t n_del, const uint32_t* del_ids, 
   if (st != FR_OK) return st;
   st = check_rows(ix, ins_emb, n_ins, false);
   if (st != FR_OK) return st;
-  st = wait_all(ix);
+  // the update runs on the index stream, behind every search in flight and
+  // ahead of every search issued after this call; the host waits for no
+  // search (only, past one staging chunk, for the previous chunk's copies)
+  st = order_after_searches(ix);
   if (st != FR_OK) return st;
-  // deletes: live bit, slot id, every term bit of the slot
-  for (uint64_t a0 = 0; a0 < n_del; a0 += ix->stage_rows) {
-    const uint64_t m = std::min<uint64_t>(ix->stage_rows, n_del - a0);
-    FR_HIP(hipMemcpyAsync(ix->d_slots, del_slots.data() + a0, m * 4, hipMemcpyHostToDevice, ix->stream));
-    LiveArgs la{};
-    la.slots = ix->d_slots;
-    la.n = m;
-    la.slot_ids = ix->slot_ids;
-    la.live = ix->live;
-    la.set = 0;
-    FR_HIP(launch_live(la, ix->stream));
-    FR_HIP(launch_clear_slot_terms(ix->d_slots, m, ix->bits, ix->cfg.vocab, ix->stream));
-    FR_HIP(hipStreamSynchronize(ix->stream));
+  std::vector<uint32_t> tmp;
+  // deletes: live bit and slot id, then exactly the slot's own term bits
+  for (uint64_t a0 = 0; a0 < n_del;) {
+    st = stage_wait(ix);
+    if (st != FR_OK) return st;
+    uint64_t m = 0, nt = 0;
+    ix->h_doff[0] = 0;
+    while (a0 + m < n_del && m < ix->ustage_rows) {
+      const uint32_t sl = del_slots[a0 + m];
+      uint64_t len = ix->t_len[sl];
+      const uint32_t* t = doc_terms(ix, ix->t_arena.data() + ix->t_off[sl], &len, tmp);
+      if (nt + len > ix->ustage_terms) break;
+      std::memcpy(ix->h_dterms + nt, t, len * 4);
+      nt += len;
+      ix->h_dslots[m++] = sl;
+      ix->h_doff[m] = nt;
+    }
+    st = enqueue_deletes(ix, m, nt);
+    if (st != FR_OK) {
+      ix->failed = true;
+      return st;
+    }
+    a0 += m;
   }
   for (uint64_t i = 0; i < n_del; ++i) {
+    const uint32_t sl = del_slots[i];
     ix->id2slot.erase(del_ids[i]);
-    ix->slot_id[del_slots[i]] = 0xFFFFFFFFu;
-    ix->free_slots.push(del_slots[i]);
+    ix->slot_id[sl] = 0xFFFFFFFFu;
+    ix->free_slots.push(sl);
+    ix->t_garbage += ix->t_len[sl];
+    ix->t_len[sl] = 0;
   }
   ix->n_live -= n_del;
   // inserts: lowest free slots first
@@ -1099,15 +1571,42 @@ fr_status fr_update_docs(fr_index* ix, uint64_t n_del, const uint32_t* del_ids, 
       slots[i] = (uint32_t)ix->hwm++;
     }
   }
-  st = write_docs(ix, n_ins, ins_emb, ins_ids, ins_term_off, ins_terms, slots.data(), 0, false);
-  if (st != FR_OK) {
-    ix->failed = true;
-    return st;
+  for (uint64_t b0 = 0; b0 < n_ins;) {
+    st = stage_wait(ix);
+    if (st != FR_OK) return st;
+    uint64_t m = 0, nt = 0;
+    ix->h_uoff[0] = 0;
+    while (b0 + m < n_ins && m < ix->ustage_rows) {
+      const uint64_t i = b0 + m;
+      uint64_t len = ins_term_off[i + 1] - ins_term_off[i];
+      const uint32_t* t = doc_terms(ix, ins_terms + ins_term_off[i], &len, tmp);
+      if (nt + len > ix->ustage_terms) break;
+      std::memcpy(ix->h_uterms + nt, t, len * 4);
+      std::memcpy(ix->h_urows + m * ix->dim, ins_emb + i * ix->dim, ix->dim * 4);
+      nt += len;
+      ix->h_uids[m] = ins_ids[i];
+      ix->h_uslots[m++] = slots[i];
+      ix->h_uoff[m] = nt;
+    }
+    st = enqueue_inserts(ix, m, nt);
+    if (st != FR_OK) {
+      ix->failed = true;
+      return st;
+    }
+    b0 += m;
   }
+  FR_HIP(hipEventRecord(ix->upd_done, ix->stream));
+  ix->upd_pending = true;
   for (uint64_t i = 0; i < n_ins; ++i) {
     ix->id2slot[ins_ids[i]] = slots[i];
     ix->slot_id[slots[i]] = ins_ids[i];
+    const uint64_t len = ins_term_off[i + 1] - ins_term_off[i];
+    ix->t_off[slots[i]] = ix->t_arena.size();
+    ix->t_len[slots[i]] = (uint32_t)len;
+    ix->t_arena.insert(ix->t_arena.end(), ins_terms + ins_term_off[i],
+                       ins_terms + ins_term_off[i] + len);
   }
+  compact_terms(ix);
   ix->n_live += n_ins;
   ix->epoch += 1;
   if (out_epoch) *out_epoch = ix->epoch;
@@ -1126,6 +1625,12 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   if (async && !dev) return fail(FR_EINVAL, "an asynchronous search needs FR_DEVICE_PTRS");
   if ((flags & FR_GRAPH) && async && !stream)
     return fail(FR_EINVAL, "FR_GRAPH cannot capture the null stream");
+  const bool pre = flags & FR_PRESELECT;
+  if (pre && (!ix->qbits || !ix->quant_set))
+    return fail(FR_EINVAL, "FR_PRESELECT needs an index created with quant_bits and an "
+                           "encoding table (fr_set_quantizer)");
+  if (pre && (flags & FR_GRAPH))
+    return fail(FR_EUNSUPPORTED, "FR_PRESELECT searches are not captured (FR_GRAPH)");
   if (n_q > ix->qmax) return fail(FR_EINVAL, "n_q exceeds max_batch");
   uint32_t n_c = 0, n_l = 0;
   fr_status st = validate_cnf(ix, n_q, cnf, &n_c, &n_l);
@@ -1138,6 +1643,8 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   Workspace* w = acquire_ws(ix, flags & FR_NOWAIT, &st);
   if (!w) return st;
   hipStream_t s = async ? (hipStream_t)stream : ix->stream;
+  st = order_after_update(ix, s);
+  if (st != FR_OK) return st;
   // inputs
   w->h_desc[0] = n_q;
   w->h_desc[1] = n_q;
@@ -1161,7 +1668,18 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
   const Choice ch = choose(ix, n_q, k, n_groups);
   ring_slot(ix, *w);
-  if (flags & FR_GRAPH) {
+  uint64_t survivors = 0;   // pre-selection: sum over queries of min(quantK, live)
+  if (pre) {
+    uint32_t max_qk = 0;
+    for (uint32_t q = 0; q < n_q; ++q) {
+      const uint32_t qk = (uint32_t)std::min<uint64_t>((uint64_t)ix->qfactor * k[q], ix->scap);
+      max_qk = std::max(max_qk, qk);
+      survivors += std::min<uint64_t>(qk, ix->n_live);
+    }
+    st = enqueue_preselect(ix, *w, s, n_groups, max_qk, true, qsrc, o_ids, o_scores, o_count,
+                           o_nm);
+    if (st != FR_OK) return st;
+  } else if (flags & FR_GRAPH) {
     // the whole device sequence as one graph, captured once per tiling,
     // corpus extent and output binding; kernels read the batch size from the
     // workspace descriptor, so any batch reuses the graph
@@ -1204,10 +1722,23 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
     std::sort(t.begin(), t.end());
     w->last_terms = (uint64_t)(std::unique(t.begin(), t.end()) - t.begin());
     w->last_live = ix->n_live;
-    const double per_doc = (double)ix->dpad * elem_bytes(ix->dt) + (ix->dt == kFP8 ? 4.0 : 0.0);
-    w->last_alg_bytes = (double)ix->n_live * per_doc + (double)ix->n_live * w->last_terms / 8.0 +
-                        (double)ix->hwm / 8.0 + (double)n_q * ix->cfg.k_max * 8.0;
-    w->last_alg_flops = 2.0 * ix->dim * n_q * (double)ix->n_live;
+    w->last_preselect = pre;
+    w->last_survivors = survivors;
+    if (pre) {
+      // one pass over the codes and predicate bits (the scan makes two),
+      // plus the survivors' FP32 rows; "flops" counts the survivors' FP32
+      // multiply-adds only (the code scores are integer work)
+      w->last_alg_bytes = (double)ix->n_live * (ix->qbits / 8.0 + w->last_terms / 8.0) +
+                          (double)ix->hwm / 8.0 + (double)survivors * ix->dpad * 4.0;
+      w->last_alg_flops = 2.0 * ix->dim * (double)survivors;
+    } else {
+      const double per_doc =
+          (double)ix->dpad * elem_bytes(ix->dt) + (ix->dt == kFP8 ? 4.0 : 0.0);
+      w->last_alg_bytes = (double)ix->n_live * per_doc +
+                          (double)ix->n_live * w->last_terms / 8.0 + (double)ix->hwm / 8.0 +
+                          (double)n_q * ix->cfg.k_max * 8.0;
+      w->last_alg_flops = 2.0 * ix->dim * n_q * (double)ix->n_live;
+    }
   }
   w->last_nq = n_q;
   ix->last_ws = (size_t)(w - ix->ws.data());
@@ -1276,6 +1807,8 @@ fr_status fr_search_noalloc(fr_index* ix, uint32_t n_q, const float* queries,
   }
   layout_host_inputs(w, ix->na_h_in);
   hipStream_t s = async ? (hipStream_t)stream : ix->stream;
+  st = order_after_update(ix, s);
+  if (st != FR_OK) return st;
   w.h_desc[0] = n_q;
   w.h_desc[1] = n_q;
   w.h_desc[2] = 0;
@@ -1289,6 +1822,13 @@ fr_status fr_search_noalloc(fr_index* ix, uint32_t n_q, const float* queries,
   st = enqueue_search(ix, w, s, ch, n_groups, false, queries, out_ids, out_scores, out_count,
                       (unsigned long long*)out_nmatch);
   if (st != FR_OK) return st;
+  // (a search captured into the caller's graph is ordered by the caller)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  FR_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs == hipStreamCaptureStatusNone) {
+    FR_HIP(hipEventRecord(ix->na_done, s));
+    ix->na_inflight = true;
+  }
   if (async) return FR_OK;
   FR_HIP(hipMemcpyAsync(ix->na_h_count, out_count, (size_t)n_q * 4, hipMemcpyDeviceToHost, s));
   FR_HIP(hipStreamSynchronize(s));
@@ -1296,6 +1836,68 @@ fr_status fr_search_noalloc(fr_index* ix, uint32_t n_q, const float* queries,
     if (ix->na_h_count[q] == 0xFFFFFFFFu)
       return fail(FR_EUNSUPPORTED,
                   "a query had more tied candidates than the candidate buffer holds (raise cand_cap)");
+  return FR_OK;
+}
+
+fr_status fr_set_quantizer(fr_index* ix, const uint32_t* bin_off, const uint32_t* bin_dim,
+                           const float* bin_sign) {
+  if (!ix) return fail(FR_EINVAL, "null index");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (ix->failed) return fail(FR_EDEVICE, "index failed earlier");
+  if (!ix->qbits) return fail(FR_EINVAL, "the index was created without quant_bits");
+  if (!bin_off) return fail(FR_EINVAL, "bin_off missing");
+  const uint32_t nb = ix->qbits;
+  if (bin_off[0] != 0) return fail(FR_EINVAL, "bin_off[0] must be 0");
+  for (uint32_t j = 0; j < nb; ++j)
+    if (bin_off[j + 1] < bin_off[j]) return fail(FR_EINVAL, "bin_off must be non-decreasing");
+  const uint64_t ne = bin_off[nb];
+  if (ne > ix->bin_cap)
+    return fail(FR_EINVAL, "more table entries (" + std::to_string(ne) + ") than bits x padded "
+                           "dimension (" + std::to_string(ix->bin_cap) + ")");
+  if (ne && (!bin_dim || !bin_sign)) return fail(FR_EINVAL, "bin_dim / bin_sign missing");
+  for (uint64_t e = 0; e < ne; ++e) {
+    if (bin_dim[e] >= ix->dim) return fail(FR_EINVAL, "bin_dim entry >= dim");
+    if (bin_sign[e] != 1.0f && bin_sign[e] != -1.0f)
+      return fail(FR_EINVAL, "bin_sign entries must be +1 or -1");
+  }
+  FR_HIP(hipSetDevice(ix->cfg.device));
+  fr_status st = wait_all(ix);
+  if (st != FR_OK) return st;
+  FR_HIP(hipMemcpyAsync(ix->d_bin_off, bin_off, (nb + 1) * 4, hipMemcpyHostToDevice, ix->stream));
+  if (ne) {
+    FR_HIP(hipMemcpyAsync(ix->d_bin_dim, bin_dim, ne * 4, hipMemcpyHostToDevice, ix->stream));
+    FR_HIP(hipMemcpyAsync(ix->d_bin_sign, bin_sign, ne * 4, hipMemcpyHostToDevice, ix->stream));
+  }
+  ix->quant_set = true;
+  // the corpus already stored: every slot from its FP32 master row
+  hipError_t e = encode_rows(ix, ix->master, ix->dpad, ix->hwm, nullptr, 0);
+  if (e == hipSuccess) e = hipStreamSynchronize(ix->stream);
+  if (e != hipSuccess) {
+    ix->failed = true;
+    return fail(FR_EDEVICE, std::string("encoding the corpus failed: ") + hipGetErrorString(e));
+  }
+  return FR_OK;
+}
+
+fr_status fr_debug_codes(fr_index* ix, uint64_t slot0, uint64_t n, uint64_t* out) {
+  if (!ix || (n && !out)) return fail(FR_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  if (!ix->qbits) return fail(FR_EINVAL, "the index has no sign codes");
+  if (slot0 + n > ix->cap) return fail(FR_EINVAL, "slot range beyond capacity");
+  FR_HIP(hipSetDevice(ix->cfg.device));
+  fr_status st = wait_all(ix);
+  if (st != FR_OK) return st;
+  const uint32_t W = ix->qbits / 64;
+  // whole 64-slot chunks covering the range, then rows in slot order
+  const uint64_t c0 = slot0 / 64, c1 = (slot0 + n + 63) / 64;
+  std::vector<uint64_t> buf((c1 - c0) * W * 64);
+  if (!buf.empty())
+    FR_HIP(hipMemcpy(buf.data(), ix->codes + c0 * W * 64, buf.size() * 8, hipMemcpyDeviceToHost));
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint64_t sl = slot0 + i;
+    for (uint32_t w = 0; w < W; ++w)
+      out[i * W + w] = buf[((sl / 64 - c0) * W + w) * 64 + sl % 64];
+  }
   return FR_OK;
 }
 
@@ -1317,6 +1919,10 @@ fr_status fr_stats(fr_index* ix, fr_search_stats* out) {
   const uint32_t passes = w.h_desc_out[2] ? 2 : 1;
   double gathers = 0;
   for (uint32_t q = 0; q < w.last_nq; ++q) {
+    if (w.last_preselect) {
+      cands += std::min(w.h_cnt[q], ix->scap);   // survivors (their rows are in alg_bytes)
+      continue;
+    }
     cands += std::min(w.h_cnt[q], ix->cand_cap);
     if (ix->dt != kF32) gathers += (double)w.h_selcnt[q] * ix->dpad * 4.0;
   }

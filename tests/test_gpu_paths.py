@@ -349,7 +349,7 @@ def test_server_rejects_bad_requests_and_reports_failed_queries():
     from paper_2402_13435_amd import FrError
     from paper_2402_13435_amd.serve import Server
     ix, row = _all_tied_index()
-    srv = Server(ix, slots=1, max_batch=4096)          # clamped to the index's max_batch
+    srv = Server(ix, max_inflight=1, max_batch=4096)          # clamped to the index's max_batch
     assert srv.max_batch == ix.max_batch
     with pytest.raises(ValueError):
         srv.submit(row[0], [], 17)                       # K > k_max

@@ -281,6 +281,61 @@ def test_updates_match_rebuilt_oracle():
     assert set(int(x) for x in slots if x != 0xFFFFFFFF) == set(int(x) for x in o.ids[o.live])
 
 
+def test_updates_are_ordered_with_asynchronous_searches():
+    """Searches and updates issued with no host synchronisation between them
+    (searches asynchronous on two streams, one through the scratch-array
+    entry point): each search sees exactly the corpus of its place in the
+    call sequence.  Every update deletes each query's current best match, so
+    a search on the wrong side of an update returns a wrong row."""
+    import copy
+    from types import SimpleNamespace
+    torch = pytest.importorskip("torch")
+    from paper_2402_13435_amd.binding import SearchResult
+    cfg = datagen.scaled(datagen.CONFIGS["tiny"], 3000, 16)
+    c = datagen.corpus(cfg)
+    qb = datagen.queries(cfg)
+    o = oracle_for(c)
+    ix = gpu_index(c, k_max=20, capacity=3600, n_workspaces=3)
+    q = torch.from_numpy(qb.emb).cuda()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    log = datagen.update_log(cfg, c.ids, 4, 200)
+    issued = []
+    for j in range(5):
+        s = streams[j % 2]
+        if j == 2:
+            out = SearchResult(torch.empty((qb.n, 20), dtype=torch.int32, device="cuda"),
+                               torch.empty((qb.n, 20), dtype=torch.float32, device="cuda"),
+                               torch.empty(qb.n, dtype=torch.int32, device="cuda"),
+                               torch.empty(qb.n, dtype=torch.int64, device="cuda"))
+            ix.search_noalloc(q, qb, 20, out, stream=s)
+        else:
+            out = ix.search(q, qb, 20, stream=s)
+        issued.append((out, copy.deepcopy(o)))
+        if j == 4:
+            break
+        best = set()
+        for qi in range(qb.n):
+            a = o.search_one(qb.emb[qi], qb.cnf(qi), 1)
+            best.update(int(x) for x in a.ids[:a.count])
+        dels = np.array(sorted(best), np.uint32)
+        u = log[j]
+        ix.update_docs(dels, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
+        o.update(dels, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
+    torch.cuda.synchronize()
+    for out, snap in issued:
+        res = SimpleNamespace(ids=out.ids.cpu().numpy().view(np.uint32),
+                              scores=out.scores.cpu().numpy(),
+                              count=out.count.cpu().numpy().view(np.uint32),
+                              n_match=out.n_match.cpu().numpy().astype(np.uint64))
+        for qi in range(qb.n):
+            check_query(snap, qb, qi, res, 20)
+    # the host term store cleared exactly the deleted documents' bits
+    full = ix.search(qb.emb, qb, 20)
+    for qi in range(qb.n):
+        check_query(o, qb, qi, full, 20)
+    ix.close()
+
+
 def test_update_errors_leave_index_unchanged(tiny):
     from paper_2402_13435_amd import FrError
     from paper_2402_13435_amd.binding import FR_ECAPACITY, FR_EDUPID, FR_ENOTFOUND

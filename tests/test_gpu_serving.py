@@ -27,7 +27,7 @@ def test_alone_equals_in_the_mix():
         r = ix.search(one.emb, one, int(ks[q]))
         alone.append((r.ids[0, :r.count[0]].copy(), r.scores[0, :r.count[0]].copy(),
                       int(r.n_match[0])))
-    srv = Server(ix, slots=3, max_batch=32)
+    srv = Server(ix, max_inflight=3, max_batch=32, max_wait_s=0.002)
     futs = []
 
     def client():
@@ -46,10 +46,60 @@ def test_alone_equals_in_the_mix():
         assert np.array_equal(rep.ids, ids), q
         assert np.array_equal(rep.scores, sc), q
         assert rep.n_match == nm
+    st = srv.stats()
     srv.close()
-    assert max(srv.batches) > 1, srv.batches          # requests were batched together
+    assert st["max_batch_seen"] > 1, st               # requests were batched together
+    assert st["queries"] == qb.n and st["failed"] == 0
     s = latency_summary(replies)
     assert s["n"] == qb.n and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_bulk_submission_matches_direct_search():
+    """submit_many / wait (the load generator's path): many requests per
+    call with arrival stamps, rows written in place, each row equal to the
+    same query searched directly; a wrapped query range and K = 0 included."""
+    from paper_2402_13435_amd import Cnf
+    from paper_2402_13435_amd.serve import ResultRows, Server, clock_ns
+    cfg = datagen.scaled(datagen.CONFIGS["fp32"], 30_000, 64)
+    c = datagen.corpus(cfg)
+    qb = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms))
+    ix = gpu_index(c, k_max=100, max_batch=48, n_workspaces=2)
+    ks = np.where(np.arange(qb.n) % 7 == 0, 0, qb.k).astype(np.uint32)
+    # the direct rows, in batches the index takes (results do not depend on
+    # the batch)
+    parts = [ix.search(qb.emb[a:a + 32], qb.subset(range(a, min(a + 32, qb.n))), ks[a:a + 32])
+             for a in range(0, qb.n, 32)]
+    direct = SimpleNamespace(ids=np.concatenate([p.ids for p in parts]),
+                             scores=np.concatenate([p.scores for p in parts]),
+                             count=np.concatenate([p.count for p in parts]),
+                             n_match=np.concatenate([p.n_match for p in parts]))
+    srv = Server(ix, max_inflight=2, max_batch=48, max_wait_s=0.002)
+    n_req = 3 * qb.n + 5
+    rows = ResultRows(n_req, ix.k_max)
+    t_arr = np.full(n_req, clock_ns(), np.uint64)
+    i, last = 0, -1
+    while i < n_req:
+        a = i % qb.n
+        e = min(n_req, i + min(qb.n - a, 37))
+        b = a + e - i
+        co = qb.clause_off[a:b + 1]
+        lo = qb.literal_off[co[0]:co[-1] + 1]
+        cnf = Cnf(co - co[0], lo - lo[0], qb.terms[lo[0]:lo[-1]])
+        last = srv.submit_many(qb.emb[a:b], cnf, ks[a:b], t_arr[i:e], rows, i) + (e - i) - 1
+        i = e
+    srv.wait(last, timeout_s=60)
+    st = srv.stats()
+    srv.close()
+    assert st["queries"] == n_req and st["failed"] == 0 and st["max_batch_seen"] <= 48
+    assert (rows.status == 0).all()
+    assert (rows.done_ns >= t_arr).all()
+    for r in range(n_req):
+        q = r % qb.n
+        cnt = int(direct.count[q])
+        assert rows.count[r] == cnt and rows.n_match[r] == direct.n_match[q], r
+        assert np.array_equal(rows.ids[r, :cnt], direct.ids[q, :cnt]), r
+        assert np.array_equal(rows.scores[r, :cnt], direct.scores[q, :cnt]), r
+    ix.close()
 
 
 def test_updates_between_batches_are_visible():
@@ -59,7 +109,7 @@ def test_updates_between_batches_are_visible():
     qb = datagen.queries(cfg)
     o = oracle_for(c)
     ix = gpu_index(c, k_max=10, capacity=5000, max_batch=16, n_workspaces=2)
-    srv = Server(ix, slots=2, max_batch=16)
+    srv = Server(ix, max_inflight=2, max_batch=16)
     log = datagen.update_log(cfg, c.ids, 2, 400)
     for u in log:
         srv.update(u.del_ids, u.ins_ids, u.ins_emb, u.ins_term_off, u.ins_terms)
