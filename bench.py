@@ -535,6 +535,12 @@ def bench_quantk(args, torch):
 
 
 def bench_serving(args, torch):
+    line = serving_leg(args, torch, args.levels, args.level_s, args.n_docs)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def serving_leg(args, torch, loads, level_s: float, n_docs: int = 0) -> dict:
     """Resident BF16 corpus, open-loop Poisson arrivals at fixed fractions of
     saturation, continuous batching by the library's request loop (fr_server:
     a batch of everything pending whenever fewer than two batches are on the
@@ -546,8 +552,8 @@ def bench_serving(args, torch):
     from paper_2402_13435_amd import Index
     from paper_2402_13435_amd.serve import Server, ResultRows, clock_ns
     cfg = datagen.CONFIGS["serving"]
-    if args.n_docs:
-        cfg = datagen.scaled(cfg, args.n_docs)
+    if n_docs:
+        cfg = datagen.scaled(cfg, n_docs)
     log(f"generating the serving workload ({cfg.n_docs} docs)")
     c = datagen.corpus(cfg)
     qb = datagen.queries(cfg, datagen.doc_frequency(cfg, c.term_off, c.terms))
@@ -564,9 +570,9 @@ def bench_serving(args, torch):
     # one update log for the whole run, applied in order across the levels
     # (each batch deletes ids that are live once the batches before it ran)
     plan = []
-    for frac in args.levels:
+    for frac in loads:
         rate = frac * sat
-        n_req = int(min(args.max_requests, max(200, rate * args.level_s)))
+        n_req = int(min(args.max_requests, max(200, rate * level_s)))
         plan.append((frac, rate, n_req))
     n_upd = sum(int(n / r / 0.1) + 20 for _, r, n in plan)
     log_live = np.asarray(c.ids[:: max(1, c.n // 100000)], dtype=np.uint32)
@@ -637,8 +643,7 @@ def bench_serving(args, torch):
         "saturation_qps": round(sat, 1), "saturation_search_ms": round(t["total_ms"], 3),
         "levels": levels, "update_errors": upd_errors, "data": "synthetic"}
     ix.close()
-    print(json.dumps(line), flush=True)
-    return 0
+    return line
 
 
 def main() -> int:
@@ -667,6 +672,10 @@ def main() -> int:
                          "(the autotuner, on a disjoint batch of the same shape)")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 10M x 256 precision leg of the default run")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the serving leg (40M docs) of the default run")
+    ap.add_argument("--c5-after-s", type=float, default=420.0,
+                    help="skip the serving leg if the run has taken longer than this")
     ap.add_argument("--c3-after-s", type=float, default=240.0,
                     help="skip the precision leg when the run has already taken this long")
     args = ap.parse_args()
@@ -839,6 +848,14 @@ def main() -> int:
         else:
             del c
             line["forms_10M"] = precision_leg(args, torch)
+    if not args.no_c5:
+        spent = time.perf_counter() - t_start
+        if spent > args.c5_after_s:
+            line["serving_40M"] = {"skipped": f"run already took {spent:.0f} s"}
+        else:
+            # the serving workload at two loads, shorter levels than
+            # --config serving
+            line["serving_40M"] = serving_leg(args, torch, (0.5, 0.9), 5.0)
     print(json.dumps(line), flush=True)
     if line.get("parity", {}).get("failed"):
         log(f"FP32 parity failures: {line['parity']}")

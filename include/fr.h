@@ -115,8 +115,10 @@ typedef struct {
   uint64_t n_terms_batch;   /* distinct terms referenced by the batch */
   double   alg_bytes;       /* algorithmic HBM bytes of the scan */
   double   alg_flops;       /* 2 * dim * n_queries * n_slots_scanned */
-  float    ms_scan;         /* device time of the scan kernel(s) */
-  float    ms_total;        /* device time from first to last kernel */
+  float    ms_scan;         /* device time of the first scan pass */
+  float    ms_total;        /* device time from the first scan pass to the last kernel */
+  uint32_t n_sparse;        /* queries the sparse routing took out of the scan */
+  float    ms_call;         /* device time from the call's first kernel to its last */
 } fr_search_stats;
 
 /* Create an index on `cfg->device` and reserve all its device memory:
@@ -407,9 +409,24 @@ fr_status fr_set_tiling(fr_index* ix, uint32_t query_blocks, uint32_t waves,
  * tighter speculative one (see fr_search).  FR_STRAT_NO_REFRESH: the scan
  * does not raise thresholds from the candidates it has found (the bucket
  * histogram of the appendix's "Fast Top K Selection"); they stay at their
- * start.  Results are identical under every strategy. */
+ * start.  Results are identical under every strategy, except that a query
+ * taken out of the scan by sparse routing gets its FP32 scores from another
+ * summation order (equal within the FP32 dot-product error bound; its ids
+ * differ only where such scores tie within it). */
 #define FR_STRAT_NO_SPECULATION 1u
 #define FR_STRAT_NO_REFRESH     2u
+/* Sparse routing, levels 1..7 (appendix "Message Passing between Layers"
+ * and "EBR": only the rows that passed the predicate are scored, which pays
+ * when few pass): a query with at most n_live * 2^(level-11) matches (0.1%
+ * at level 1, 6.25% at level 7), and, for BF16/FP8 indexes, at most its
+ * selection size R_q, skips the scan; its matching rows are listed from the
+ * predicate masks and scored one by one in FP32, then selected exactly.  The
+ * results are the same as without routing (for BF16/FP8 all of such a
+ * query's matches are within its R_q, so its FP32 top K is what the
+ * rescoring of the scan's candidates gives).  Not used by
+ * fr_search_noalloc. */
+#define FR_STRAT_SPARSE(level)  ((uint32_t)(level) << 4)
+#define FR_STRAT_SPARSE_MASK    0xF0u
 
 /* Set the search strategy: with `pinned` nonzero it is used for every search;
  * otherwise it is the default that tuned choices override.  FR_EINVAL for

@@ -24,6 +24,11 @@ STATUS_NAMES = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_ECAPACITY"
                 -7: "FR_EDEVICE", -8: "FR_EBUSY"}
 FR_DEVICE_PTRS, FR_NOWAIT, FR_GRAPH, FR_ASYNC, FR_PRESELECT = 1, 2, 4, 8, 16
 FR_STRAT_NO_SPECULATION, FR_STRAT_NO_REFRESH = 1, 2
+
+
+def FR_STRAT_SPARSE(level: int) -> int:
+    """Sparse routing level 1..7 (see include/fr.h)."""
+    return int(level) << 4
 DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -53,7 +58,8 @@ class FrStats(ctypes.Structure):
                 ("candidates", ctypes.c_uint64), ("n_live", ctypes.c_uint64),
                 ("n_terms_batch", ctypes.c_uint64), ("alg_bytes", ctypes.c_double),
                 ("alg_flops", ctypes.c_double), ("ms_scan", ctypes.c_float),
-                ("ms_total", ctypes.c_float)]
+                ("ms_total", ctypes.c_float), ("n_sparse", ctypes.c_uint32),
+                ("ms_call", ctypes.c_float)]
 
 
 class FrServerConfig(ctypes.Structure):

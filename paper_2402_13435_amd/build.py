@@ -20,7 +20,8 @@ HIP_FLAGS = [
     "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-I" + INCLUDE, "-I" + CSRC,
 ]
-SOURCES = ["fr_kernels.hip", "fr_quant.hip", "fr_runtime.cpp", "fr_server.cpp"]
+SOURCES = ["fr_kernels.hip", "fr_quant.hip", "fr_sparse.hip", "fr_runtime.cpp",
+           "fr_server.cpp"]
 
 
 def hipcc() -> str:

@@ -38,6 +38,13 @@ constexpr float kSpecL = 9.2103404f;
 // start).
 constexpr uint32_t kStratNoSpec = 1u;
 constexpr uint32_t kStratNoRefresh = 2u;
+// bits 4-7: sparse routing level L (0: off).  Queries with at most
+// n_live * 2^(L-11) matches (and at most the selection size K' for the
+// reduced-precision forms) skip the scan: their matching rows are listed
+// from the masks and scored one by one in FP32.
+constexpr uint32_t kStratSparseShift = 4u;
+constexpr uint32_t kStratSparseMask = 0xF0u;
+constexpr uint32_t kSparseMaxLevel = 7u;
 constexpr int kLits = 12;            // literals per query in the scan's fast mask path
 // device scratch of fr_search_noalloc (one array per device, in the code
 // object) and the device ordinals it is looked up for
@@ -147,6 +154,7 @@ struct MaskWordArgs {
   uint64_t* mw;
   unsigned long long* nmatch;
   uint32_t count_matches;
+  const uint32_t* run_if;  // device flag, or null: when *run_if == 0 the pass does nothing
 };
 
 // Starting thresholds: for each query of the first pass, the K'-th best
@@ -339,19 +347,59 @@ struct QuantSelectArgs {
   uint32_t* ovf;
 };
 
-struct QuantDotArgs {
+// FP32 inner products of listed rows (the pre-selection's survivors, or a
+// sparse-routed query's matches) against the query: row i of query q is
+// slot rows[q * stride + i], i < cnt[q]; cnt[q] > stride marks a failed query
+// (skipped).  Queries are y < max_q, or qlist[y] for y < *n_list when a
+// list is given.
+struct RowDotArgs {
   uint32_t max_q;
   const uint32_t* n_dev;
+  const uint32_t* qlist;   // or null
+  const uint32_t* n_list;
   const uint32_t* cnt;
-  const uint32_t* surv;
-  uint32_t scap;
-  uint32_t max_cnt;        // grid size: most survivors of any query of the batch
-  const float* master;     // [slot][dpad]
+  const uint32_t* rows;
+  uint32_t stride;
+  uint32_t max_cnt;        // grid size: most rows of any query
+  const float* master;     // [slot][dpad], or null: FP32 embedding tiles
+  const uint8_t* tiles;
   uint32_t dpad;
   const float* qrows;      // [q][q_ld]
   uint32_t q_ld;
   uint32_t dim;
-  unsigned long long* key; // [q][scap]: FP32 score key << 32 | slot
+  unsigned long long* key; // [q][key_stride]: FP32 score key << 32 | slot
+  uint32_t key_stride;     // >= stride
+};
+
+// Sparse routing: split the batch (queries 0..n-1, whose masks were just
+// computed at position = query) into the scan's list and the sparse list,
+// keeping query order in both.
+struct RouteArgs {
+  uint32_t max_q;
+  const uint32_t* n_dev;
+  const unsigned long long* nmatch;
+  const uint32_t* kp;      // with cap_by_kp: a query routes only if n_match <= kp
+  int cap_by_kp;
+  uint32_t limit;          // route queries with n_match <= limit
+  uint32_t* qlist;         // out: the scan's queries
+  uint32_t* n_list;
+  uint32_t* slist;         // out: the sparse queries
+  uint32_t* n_slist;
+};
+
+// The matching slots of each sparse query, from its mask words (stored at
+// position = query), appended to rows[q * cap ...] with cnt[q] counting.
+struct SparseRowsArgs {
+  uint32_t max_q;
+  const uint32_t* slist;
+  const uint32_t* n_slist;
+  const uint64_t* mw;
+  uint32_t ppad;
+  uint32_t n_groups;
+  uint32_t gpb;            // groups per block
+  uint32_t* cnt;
+  uint32_t* rows;
+  uint32_t cap;
 };
 
 // Codes of a.n rows.
@@ -367,8 +415,10 @@ hipError_t launch_quant_collect(const QuantArgs& a, hipStream_t s);
 // The `need` lowest-id ties join the survivors; a failed query gets a count
 // above scap (the exact selection then marks it failed).
 hipError_t launch_quant_ties(const QuantSelectArgs& a, hipStream_t s);
-// FP32 inner products of the survivors against the master rows.
-hipError_t launch_quant_dots(const QuantDotArgs& a, hipStream_t s);
+// FP32 inner products of listed rows (fr_sparse.hip).
+hipError_t launch_row_dots(const RowDotArgs& a, hipStream_t s);
+hipError_t launch_route(const RouteArgs& a, hipStream_t s);
+hipError_t launch_sparse_rows(const SparseRowsArgs& a, hipStream_t s);
 
 // Launchers (fr_kernels.hip).  Each returns the HIP error of the launch.
 hipError_t launch_tile_rows(const TileRowsArgs& a, hipStream_t s);

@@ -428,6 +428,7 @@ hipError_t launch_query_prep(const TileRowsArgs& t, const PrepArgs& a, hipStream
 // that the scan reads one word of consecutive queries from consecutive
 // addresses.
 __global__ __launch_bounds__(256) void k_mask_words(MaskWordArgs a) {
+  if (a.run_if && *a.run_if == 0u) return;
   const uint32_t part = threadIdx.x & 7u;
   const uint32_t pos = blockIdx.x * 32u + (threadIdx.x >> 3);
   const uint32_t n = *a.n_list;

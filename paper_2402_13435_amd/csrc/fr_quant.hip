@@ -3,8 +3,8 @@
 // n_bits sign bits per document, a scan that scores every predicate match by
 // the number of code bits it shares with the query (popcount of the
 // complemented XOR), the quantK = factor * k best matches kept, and the FP32
-// inner product of those survivors only; the exact top-K of the survivors is
-// then the search kernels' exact selection.
+// inner product of those survivors only (k_row_dots, fr_sparse.hip); the
+// exact top-K of the survivors is then the search kernels' exact selection.
 //
 // The popcount score is integer and small (0..n_bits), so the cut is exact
 // without any speculation: a histogram pass counts, per query, the matches
@@ -313,44 +313,6 @@ hipError_t launch_quant_ties(const QuantSelectArgs& a, hipStream_t s) {
   FR_REQUIRE(a.slot_ids);
   if (!a.max_q) return hipSuccess;
   hipLaunchKernelGGL(k_quant_ties, dim3(a.max_q), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------- exact scores
-// One wavefront per survivor row: lane l multiplies coordinates l, l+64, ...
-// (FP32 FMA), then a fixed butterfly sums the lanes.  Blocks of 4
-// wavefronts cover 64 survivors of one query (grid.y = query).
-__global__ __launch_bounds__(256) void k_quant_dots(QuantDotArgs a) {
-  const uint32_t q = blockIdx.y;
-  const uint32_t nq = min(*a.n_dev, a.max_q);
-  if (q >= nq) return;
-  const uint32_t c = a.cnt[q];
-  if (c > a.scap) return;   // failed query
-  const int lane = threadIdx.x & 63;
-  const float* qr = a.qrows + (uint64_t)q * a.q_ld;
-  const uint32_t* sv = a.surv + (uint64_t)q * a.scap;
-  const uint32_t i0 = blockIdx.x * 64u + (threadIdx.x >> 6) * 16u;
-  for (uint32_t i = i0; i < min(i0 + 16u, c); ++i) {
-    const uint32_t slot = sv[i];
-    const float* xr = a.master + (uint64_t)slot * a.dpad;
-    float p = 0.f;
-    for (uint32_t d = (uint32_t)lane; d < a.dim; d += 64u) p = fmaf(xr[d], qr[d], p);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off);
-    if (lane == 0)
-      a.key[(uint64_t)q * a.scap + i] = ((unsigned long long)fkey(p) << 32) | slot;
-  }
-}
-hipError_t launch_quant_dots(const QuantDotArgs& a, hipStream_t s) {
-  FR_REQUIRE(a.n_dev);
-  FR_REQUIRE(a.cnt);
-  FR_REQUIRE(a.surv);
-  FR_REQUIRE(a.master);
-  FR_REQUIRE(a.qrows);
-  FR_REQUIRE(a.key);
-  if (!a.max_q || !a.max_cnt) return hipSuccess;
-  if (a.dim > a.dpad || a.q_ld < a.dim || a.max_cnt > a.scap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_quant_dots, dim3((a.max_cnt + 63) / 64, a.max_q), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

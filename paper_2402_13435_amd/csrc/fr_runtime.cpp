@@ -136,12 +136,16 @@ struct Workspace {
   uint32_t* surv = nullptr;    // [q][scap]
   uint32_t* ties = nullptr;    // [q][tcap]
   unsigned long long* qkey = nullptr;   // [q][scap]
+  // sparse routing: the sparse queries and their matching rows
+  uint32_t* slist = nullptr;
+  uint32_t* srows = nullptr;   // [q][rcap]
   bool last_preselect = false;
   uint64_t last_survivors = 0;
   hipEvent_t done = nullptr, e_scan0 = nullptr, e_scan1 = nullptr, e_end = nullptr;
+  hipEvent_t e_start = nullptr;   // first kernel of the call
   // timing ring: scan start / scan end / end of the search, per recent call
   static constexpr int kRing = 64;
-  hipEvent_t r0[kRing] = {}, r1[kRing] = {}, r2[kRing] = {};
+  hipEvent_t r0[kRing] = {}, r1[kRing] = {}, r2[kRing] = {}, r3[kRing] = {};
   uint64_t n_calls = 0;
   // captured search sequence (FR_GRAPH), valid for one tiling / corpus
   // extent / output binding
@@ -270,6 +274,16 @@ void carve(T** p, uint8_t* base, size_t& off, size_t count) {
 // `base` (256-byte aligned pieces); `outputs` adds the result buffers that
 // host-pointer searches copy back from.  Sets the workspace's sizes and
 // returns the block's size; with base == nullptr it only computes it.
+bool strategy_ok(uint32_t st) {
+  return !(st & ~(uint32_t)(FR_STRAT_NO_SPECULATION | FR_STRAT_NO_REFRESH | FR_STRAT_SPARSE_MASK)) &&
+         ((st & FR_STRAT_SPARSE_MASK) >> 4) <= kSparseMaxLevel;
+}
+
+// Most rows a sparse-routed query can have: the candidate buffer (FP32), or
+// the selection size R (the reduced-precision forms route a query only when
+// all its matches fit in R, so their result is the one the scan would give).
+uint32_t sparse_cap(const fr_index* ix) { return ix->dt == kF32 ? ix->cand_cap : ix->rmax; }
+
 size_t layout_workspace(const fr_index* ix, Workspace& w, uint8_t* base, uint32_t qm,
                         uint32_t cm, uint32_t lm, uint64_t n_groups, uint32_t cand_cap,
                         bool outputs) {
@@ -314,6 +328,10 @@ size_t layout_workspace(const fr_index* ix, Workspace& w, uint8_t* base, uint32_
   carve(&w.mw, base, off, (size_t)std::max<uint64_t>(n_groups, 1) * kWords * w.ppad);
   carve(&w.sel_key, base, off, (size_t)qm * ix->rmax);
   carve(&w.sel_slot, base, off, (size_t)qm * ix->rmax);
+  if (outputs) {
+    carve(&w.slist, base, off, qm);
+    carve(&w.srows, base, off, (size_t)qm * sparse_cap(ix));
+  }
   if (outputs && ix->qbits) {
     carve(&w.qcode, base, off, (size_t)qm * (ix->qbits / 64));
     carve(&w.qhist, base, off, (size_t)qm * (ix->qbits + 1));
@@ -775,6 +793,7 @@ MaskWordArgs mask_args(const fr_index* ix, Workspace& w, uint32_t n_groups) {
   ma.mw = w.mw;
   ma.nmatch = w.nmatch;
   ma.count_matches = 1;
+  ma.run_if = nullptr;   // the first pass always runs
   return ma;
 }
 
@@ -784,6 +803,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
   // query rows: the workspace's padded copy (host queries), or the caller's
   // device rows, of which the kernel then writes the padded copy that the
   // FP32 rescoring reads
+  if (timing) FR_HIP(hipEventRecord(w.e_start, s));
   TileRowsArgs ta{};
   const bool in_place = qsrc != w.qrow;
   ta.rows = qsrc;
@@ -799,6 +819,105 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
   FR_HIP(launch_query_prep(ta, prep_args(ix, w), s));
   const MaskWordArgs ma = mask_args(ix, w, n_groups);
   FR_HIP(launch_mask_words(ma, s));
+
+  SelectArgs se{};
+  se.qlist = w.qlist;
+  se.n_list = w.desc + 1;
+  se.max_list = w.qcap;
+  se.final_pass = 0;
+  se.kp = w.kp;
+  se.tau = w.tau;
+  se.cnt = w.cnt;
+  se.smax = w.smax;
+  se.hist = w.hist;
+  se.hlo = w.hlo;
+  se.hinvw = w.hinvw;
+  se.qlist2 = w.qlist2;
+  se.n_list2 = w.desc + 2;
+  se.work = w.work;
+  se.qnorm = w.qnorm;
+  se.norm_max = ix->norm_max;
+  se.cand_key = w.cand_key;
+  se.slot_ids = ix->slot_ids;
+  se.cap = w.cand_cap;
+  se.sel_key = w.sel_key;
+  se.sel_slot = w.sel_slot;
+  se.sel_cnt = w.sel_cnt;
+  se.rmax = ix->rmax;
+  se.ovf = w.ovf;
+  se.tsafe = w.tsafe;
+  se.write_out = ix->dt == kF32;
+  se.k = w.k;
+  se.k_max = ix->cfg.k_max;
+  se.out_ids = o_ids;
+  se.out_scores = o_scores;
+  se.out_count = o_count;
+  se.nmatch = w.nmatch;
+  se.out_nmatch = o_nmatch;
+
+  // Sparse routing (strategy level L > 0): queries with at most
+  // n_live * 2^(L-11) matches leave the scan's list; their matching rows are
+  // listed from this pass's masks (stored at position = query) and scored
+  // one by one in FP32, and the exact selection takes their top K'.  The
+  // masks are then laid out again for the scan's shorter list (a pass that
+  // does nothing when no query was routed).
+  const uint32_t lvl = (ch.strat & kStratSparseMask) >> kStratSparseShift;
+  if (lvl && w.srows) {
+    const uint32_t rcap = sparse_cap(ix);
+    const uint32_t limit = (uint32_t)std::min<double>(
+        std::ldexp((double)ix->n_live, (int)lvl - 11), (double)rcap);
+    RouteArgs ra{};
+    ra.max_q = w.qcap;
+    ra.n_dev = w.desc;
+    ra.nmatch = w.nmatch;
+    ra.kp = w.kp;
+    ra.cap_by_kp = ix->dt != kF32;
+    ra.limit = limit;
+    ra.qlist = w.qlist;
+    ra.n_list = w.desc + 1;
+    ra.slist = w.slist;
+    ra.n_slist = w.desc + 3;
+    FR_HIP(launch_route(ra, s));
+    SparseRowsArgs sr{};
+    sr.max_q = w.qcap;
+    sr.slist = w.slist;
+    sr.n_slist = w.desc + 3;
+    sr.mw = w.mw;
+    sr.ppad = ma.ppad;
+    sr.n_groups = n_groups;
+    sr.gpb = 16;
+    sr.cnt = w.cnt;
+    sr.rows = w.srows;
+    sr.cap = rcap;
+    FR_HIP(launch_sparse_rows(sr, s));
+    RowDotArgs rd{};
+    rd.max_q = w.qcap;
+    rd.n_dev = w.desc;
+    rd.qlist = w.slist;
+    rd.n_list = w.desc + 3;
+    rd.cnt = w.cnt;
+    rd.rows = w.srows;
+    rd.stride = rcap;
+    rd.max_cnt = limit;
+    rd.master = ix->master;
+    rd.tiles = ix->master ? nullptr : ix->tiles;
+    rd.dpad = ix->dpad;
+    rd.qrows = qsrc;
+    rd.q_ld = in_place ? ix->dim : ix->dpad;
+    rd.dim = ix->dim;
+    rd.key = w.cand_key;
+    rd.key_stride = w.cand_cap;
+    FR_HIP(launch_row_dots(rd, s));
+    SelectArgs ss = se;
+    ss.qlist = w.slist;
+    ss.n_list = w.desc + 3;
+    ss.final_pass = 1;
+    FR_HIP(launch_select(ss, s));
+    MaskWordArgs mr = ma;
+    mr.count_matches = 0;
+    mr.run_if = w.desc + 3;
+    FR_HIP(launch_mask_words(mr, s));
+  }
 
   SeedArgs sd{};
   sd.qlist = w.qlist;
@@ -853,41 +972,6 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
   if (timing) FR_HIP(hipEventRecord(w.e_scan0, s));
   FR_HIP(launch_scan(sa, ix->dt, ix->dpad, ch.qb, ch.nw, ix->n_wg, s));
   if (timing) FR_HIP(hipEventRecord(w.e_scan1, s));
-
-  SelectArgs se{};
-  se.qlist = w.qlist;
-  se.n_list = w.desc + 1;
-  se.max_list = w.qcap;
-  se.final_pass = 0;
-  se.kp = w.kp;
-  se.tau = w.tau;
-  se.cnt = w.cnt;
-  se.smax = w.smax;
-  se.hist = w.hist;
-  se.hlo = w.hlo;
-  se.hinvw = w.hinvw;
-  se.qlist2 = w.qlist2;
-  se.n_list2 = w.desc + 2;
-  se.work = w.work;
-  se.qnorm = w.qnorm;
-  se.norm_max = ix->norm_max;
-  se.cand_key = w.cand_key;
-  se.slot_ids = ix->slot_ids;
-  se.cap = w.cand_cap;
-  se.sel_key = w.sel_key;
-  se.sel_slot = w.sel_slot;
-  se.sel_cnt = w.sel_cnt;
-  se.rmax = ix->rmax;
-  se.ovf = w.ovf;
-  se.tsafe = w.tsafe;
-  se.write_out = ix->dt == kF32;
-  se.k = w.k;
-  se.k_max = ix->cfg.k_max;
-  se.out_ids = o_ids;
-  se.out_scores = o_scores;
-  se.out_count = o_count;
-  se.nmatch = w.nmatch;
-  se.out_nmatch = o_nmatch;
   FR_HIP(launch_select(se, s));
 
   // second pass for the queries the first could not answer (an empty list
@@ -939,6 +1023,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
 fr_status enqueue_preselect(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_groups,
                             uint32_t max_qk, bool timing, const float* qsrc, uint32_t* o_ids,
                             float* o_scores, uint32_t* o_count, unsigned long long* o_nm) {
+  if (timing) FR_HIP(hipEventRecord(w.e_start, s));
   TileRowsArgs ta{};
   const bool in_place = qsrc != w.qrow;
   ta.rows = qsrc;
@@ -1019,12 +1104,12 @@ fr_status enqueue_preselect(fr_index* ix, Workspace& w, hipStream_t s, uint32_t 
   if (timing) FR_HIP(hipEventRecord(w.e_scan1, s));
   FR_HIP(launch_quant_ties(qc, s));
 
-  QuantDotArgs qd{};
+  RowDotArgs qd{};
   qd.max_q = w.qcap;
   qd.n_dev = w.desc;
   qd.cnt = w.cnt;
-  qd.surv = w.surv;
-  qd.scap = ix->scap;
+  qd.rows = w.surv;
+  qd.stride = ix->scap;
   qd.max_cnt = max_qk;
   qd.master = ix->master;
   qd.dpad = ix->dpad;
@@ -1032,7 +1117,8 @@ fr_status enqueue_preselect(fr_index* ix, Workspace& w, hipStream_t s, uint32_t 
   qd.q_ld = q_ld;
   qd.dim = ix->dim;
   qd.key = w.qkey;
-  FR_HIP(launch_quant_dots(qd, s));
+  qd.key_stride = ix->scap;
+  FR_HIP(launch_row_dots(qd, s));
 
   SelectArgs se{};
   se.qlist = w.qlist;
@@ -1078,6 +1164,7 @@ void ring_slot(fr_index* ix, Workspace& w) {
   const int slot = (int)(w.n_calls % Workspace::kRing);
   w.e_scan0 = w.r0[slot];
   w.e_scan1 = w.r1[slot];
+  w.e_start = w.r3[slot];
   w.e_end = w.r2[slot];
   w.n_calls += 1;
   ix->history.emplace_back((uint32_t)(&w - ix->ws.data()), (uint32_t)slot);
@@ -1338,7 +1425,7 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     bool ev_ok = hipEventCreate(&w.done) == hipSuccess;
     for (int i = 0; i < Workspace::kRing && ev_ok; ++i)
       ev_ok = hipEventCreate(&w.r0[i]) == hipSuccess && hipEventCreate(&w.r1[i]) == hipSuccess &&
-              hipEventCreate(&w.r2[i]) == hipSuccess;
+              hipEventCreate(&w.r2[i]) == hipSuccess && hipEventCreate(&w.r3[i]) == hipSuccess;
     if (!ev_ok) {
       cleanup();
       return fail(FR_EDEVICE, "hipEventCreate failed");
@@ -1398,6 +1485,7 @@ fr_status fr_destroy(fr_index* ix) {
         if (w.r0[i]) (void)hipEventDestroy(w.r0[i]);
         if (w.r1[i]) (void)hipEventDestroy(w.r1[i]);
         if (w.r2[i]) (void)hipEventDestroy(w.r2[i]);
+        if (w.r3[i]) (void)hipEventDestroy(w.r3[i]);
       }
     }
     if (ix->na_copied) {
@@ -1699,6 +1787,7 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
       FR_HIP(hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0));
       std::memcpy(w->gkey, key, sizeof key);
     }
+    FR_HIP(hipEventRecord(w->e_start, s));
     FR_HIP(hipEventRecord(w->e_scan0, s));
     FR_HIP(hipGraphLaunch(w->gexec, s));
     FR_HIP(hipEventRecord(w->e_scan1, s));
@@ -1935,6 +2024,8 @@ fr_status fr_stats(fr_index* ix, fr_search_stats* out) {
   float ms = 0;
   if (hipEventElapsedTime(&ms, w.e_scan0, w.e_scan1) == hipSuccess) s.ms_scan = ms;
   if (hipEventElapsedTime(&ms, w.e_scan0, w.e_end) == hipSuccess) s.ms_total = ms;
+  if (hipEventElapsedTime(&ms, w.e_start, w.e_end) == hipSuccess) s.ms_call = ms;
+  s.n_sparse = w.last_preselect ? 0u : w.h_desc_out[3];
   *out = s;
   return FR_OK;
 }
@@ -2096,8 +2187,7 @@ fr_status fr_set_tiling(fr_index* ix, uint32_t query_blocks, uint32_t waves,
 
 fr_status fr_set_strategy(fr_index* ix, uint32_t strategy, int pinned) {
   if (!ix) return fail(FR_EINVAL, "null index");
-  if (strategy & ~(uint32_t)(FR_STRAT_NO_SPECULATION | FR_STRAT_NO_REFRESH))
-    return fail(FR_EINVAL, "unknown strategy bits");
+  if (!strategy_ok(strategy)) return fail(FR_EINVAL, "unknown strategy bits");
   std::lock_guard<std::mutex> lk(ix->mu);
   ix->strat = strategy;
   ix->strat_pinned = pinned != 0;
@@ -2140,7 +2230,7 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
       fr_search_stats s{};
       st = fr_stats(ix, &s);
       if (st != FR_OK) return st;
-      if (rep) t.push_back(s.ms_total);
+      if (rep) t.push_back(s.ms_call);
     }
     std::sort(t.begin(), t.end());
     *ms = t[t.size() / 2];
@@ -2198,6 +2288,30 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
     }
   }
   std::sort(trials.begin(), trials.end(), by_ms);
+  // Round 3: sparse routing levels on the winner (3 searches each), the
+  // fastest level again with 9 against the winner without routing.
+  {
+    Trial base = trials[0], lv_best = base;
+    lv_best.ms = INFINITY;
+    for (uint32_t lv = 1; lv <= kSparseMaxLevel; ++lv) {
+      Trial t = base;
+      t.strat = (base.strat & ~FR_STRAT_SPARSE_MASK) | FR_STRAT_SPARSE(lv);
+      fr_status st = timed(t.qb, t.nw, t.g, t.strat, 3, &t.ms);
+      if (st != FR_OK) {
+        restore();
+        return st;
+      }
+      if (t.ms < lv_best.ms) lv_best = t;
+    }
+    if (lv_best.ms < base.ms) {
+      fr_status st = timed(lv_best.qb, lv_best.nw, lv_best.g, lv_best.strat, 9, &lv_best.ms);
+      if (st != FR_OK) {
+        restore();
+        return st;
+      }
+      if (lv_best.ms < base.ms) trials[0] = lv_best;
+    }
+  }
   const float best = trials[0].ms;
   const int best_qb = trials[0].qb, best_nw = trials[0].nw, best_g = trials[0].g;
   const uint32_t best_s = trials[0].strat;
@@ -2277,7 +2391,7 @@ fr_status fr_tuning_load(fr_index* ix, const char* path, uint32_t* out_loaded) {
     if (std::strcmp(arch, ix->arch) || dt != ix->dt || dim != ix->dim || vocab != ix->cfg.vocab)
       continue;                                 // tuned for another index shape
     if (!scan_supported(ix->dt, ix->dpad, qb, nw) || g < 0 || g > 64 ||
-        (strat & ~(unsigned)(FR_STRAT_NO_SPECULATION | FR_STRAT_NO_REFRESH)))
+        !strategy_ok(strat))
       continue;
     ix->tuned[std::make_tuple(qk, kk, sk)] = fr_index::Tuned{qb, nw, g, strat, ms};
     ++n;
