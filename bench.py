@@ -534,6 +534,47 @@ def bench_quantk(args, torch):
     return 0
 
 
+def bench_sparse(args, torch):
+    """Sparse routing on the FP32 workload's corpus (1M x 128, vocab 4,096,
+    K=100): QPS of back-to-back searches and the device time of one call at
+    routing levels 0 (off), 3, 5 and 7, for the benchmark's batch of 256
+    queries at 0.1%-50% selectivity, for the 64 most selective queries of a
+    2,048-query pool of the same recipe, and for one of those alone; FP32,
+    and BF16 with R=100."""
+    import datagen
+    from paper_2402_13435_amd import Index
+    from paper_2402_13435_amd.binding import FR_STRAT_NO_REFRESH, FR_STRAT_SPARSE
+    c, qb = datagen.workload("fp32")
+    df = datagen.doc_frequency(c.cfg, c.term_off, c.terms)
+    pool = datagen.queries(c.cfg, df, n_queries=2048)
+    order = np.argsort(np.nan_to_num(pool.target_sel, nan=1.0), kind="stable")
+    sel64 = pool.subset(order[:64].tolist())
+    batches = {"mixed256": qb, "selective64": sel64, "selective1": sel64.subset([0])}
+    points = []
+    for dt, r in (("f32", 0), ("bf16", 100)):
+        ix = Index(c.n, c.cfg.dim, c.cfg.vocab, 100, dtype=dt, rescore_r=r, max_batch=256,
+                   n_workspaces=2)
+        ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
+        for name, b in batches.items():
+            for lv in (0, 3, 5, 7):
+                ix.set_strategy(FR_STRAT_NO_REFRESH | FR_STRAT_SPARSE(lv), pinned=True)
+                t = timed_search(torch, ix, b, 100, args.steps, args.warmup)
+                st = t["stats"]
+                points.append({"dtype": dt, "batch": name, "q": b.n, "level": lv,
+                               "qps": round(t["qps"], 1), "ms_call": round(st.ms_call, 4),
+                               "routed": int(st.n_sparse),
+                               "median_n_match": int(np.median(t["n_match"]))})
+                log(json.dumps(points[-1]))
+        ix.close()
+    line = {"metric": "sparse routing: QPS and device ms per search by routing level",
+            "config": {"workload": f"sparse: {c.n:,} docs x {c.cfg.dim}-d, vocab {c.cfg.vocab}, "
+                                   "K=100; batches: 256 queries at 0.1%-50% selectivity, the 64 "
+                                   "most selective of 2,048, one of those; BF16 with R=100",
+                       "n_docs": c.n}, "points": points, "data": "synthetic"}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_serving(args, torch):
     line = serving_leg(args, torch, args.levels, args.level_s, args.n_docs)
     print(json.dumps(line), flush=True)
@@ -655,7 +696,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--config", default="fp32",
-                    choices=["fp32", "precision", "batching", "serving", "qsweep", "quantk"],
+                    choices=["fp32", "precision", "batching", "serving", "qsweep", "quantk",
+                             "sparse"],
                     help="workload (default fp32: the benchmark line)")
     ap.add_argument("--n-docs", type=int, default=0, help="resize the corpus (non-default configs)")
     ap.add_argument("--q-sizes", default="1,8,32,64,128,256,512,1024",
@@ -700,6 +742,8 @@ def main() -> int:
         return bench_serving(args, torch)
     if args.config == "quantk":
         return bench_quantk(args, torch)
+    if args.config == "sparse":
+        return bench_sparse(args, torch)
     t_start = time.perf_counter()
     log("generating the fp32 workload (1M docs x 128, 256 queries + a tuning batch)")
     c, qb = datagen.workload("fp32")

@@ -71,7 +71,8 @@ typedef enum {
 typedef struct {
   uint64_t capacity;       /* maximum live documents (slots); rounded up to 1024 */
   uint32_t dim;            /* embedding dimension, 1..256 (padded to 64 inside) */
-  uint32_t vocab;          /* term ids are in [0, vocab), vocab <= 1<<20 */
+  uint32_t vocab;          /* term ids are in [0, vocab); vocab <= 1<<20 with per-term
+                              bitmaps, <= 1<<31 with list_terms */
   uint32_t k_max;          /* largest K a query may ask for, 1..4096 */
   uint32_t rescore_r;      /* BF16/FP8: most approximate candidates rescored in
                               FP32 per query (R), k_max..4096; 0 -> 4096.
@@ -90,6 +91,15 @@ typedef struct {
                               0 (none), 64, 128, 256 or 512 (the paper's choice) */
   uint32_t quant_factor;   /* FR_PRESELECT keeps quantK = min(quant_factor * k[q], 65536)
                               documents per query (0 -> 200, the paper's choice) */
+  uint32_t list_terms;     /* 0: per-term document bitmaps (vocab / 8 bytes per document).
+                              L > 0: each document's terms as a list of at most L ids
+                              (4 L bytes per document; appendix "TBR": attribute values
+                              padded to maxNumAttr), for large vocabularies.  A search
+                              then builds bitmaps of its batch's distinct terms only
+                              (at most batch_terms) from the lists, before the mask pass.
+                              At most 4096 */
+  uint32_t batch_terms;    /* list_terms only: most distinct terms in one search batch,
+                              1..1024 (0 -> 1024); a larger batch fails with FR_EINVAL */
 } fr_config;
 
 /* A batch of CNF predicates in CSR-of-CSR form (host memory):

@@ -45,7 +45,8 @@ class FrConfig(ctypes.Structure):
                 ("max_clauses", ctypes.c_uint32), ("max_literals", ctypes.c_uint32),
                 ("n_workspaces", ctypes.c_uint32), ("cand_cap", ctypes.c_uint32),
                 ("device", ctypes.c_int), ("quant_bits", ctypes.c_uint32),
-                ("quant_factor", ctypes.c_uint32)]
+                ("quant_factor", ctypes.c_uint32), ("list_terms", ctypes.c_uint32),
+                ("batch_terms", ctypes.c_uint32)]
 
 
 class FrCnfBatch(ctypes.Structure):
@@ -230,11 +231,11 @@ class Index:
                  rescore_r: int = 0, rescore_min: int = 0, max_batch: int = 1024,
                  max_clauses: int = 0, max_literals: int = 0, n_workspaces: int = 1,
                  cand_cap: int = 0, device: int = 0, quant_bits: int = 0,
-                 quant_factor: int = 0):
+                 quant_factor: int = 0, list_terms: int = 0, batch_terms: int = 0):
         self._h = None
         cfg = FrConfig(capacity, dim, vocab, k_max, rescore_r, rescore_min, DTYPES[dtype],
                        max_batch, max_clauses, max_literals, n_workspaces, cand_cap, device,
-                       quant_bits, quant_factor)
+                       quant_bits, quant_factor, list_terms, batch_terms)
         h = _vp()
         _check(lib().fr_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -243,6 +244,8 @@ class Index:
         self.max_batch = max_batch
         self.n_workspaces = max(1, n_workspaces)
         self.quant_bits = quant_bits
+        self.list_terms = list_terms
+        self.batch_terms = (batch_terms or 1024) if list_terms else 0
         self.quant_factor = quant_factor or 200
 
     # ----------------------------------------------------------- lifecycle

@@ -20,7 +20,7 @@ HIP_FLAGS = [
     "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-I" + INCLUDE, "-I" + CSRC,
 ]
-SOURCES = ["fr_kernels.hip", "fr_quant.hip", "fr_sparse.hip", "fr_runtime.cpp",
+SOURCES = ["fr_kernels.hip", "fr_quant.hip", "fr_sparse.hip", "fr_lists.hip", "fr_runtime.cpp",
            "fr_server.cpp"]
 
 

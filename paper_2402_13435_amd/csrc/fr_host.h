@@ -14,6 +14,7 @@ struct IndexShape {
   uint32_t dim, vocab, k_max;
   uint32_t max_batch, max_clauses, max_literals;  // per fr_search call
   uint32_t n_workspaces;
+  uint32_t batch_terms;    // term lists: most distinct terms per search (0: no limit)
   int device;
 };
 fr_status index_shape(fr_index* ix, IndexShape* out);

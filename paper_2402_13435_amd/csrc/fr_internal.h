@@ -420,6 +420,40 @@ hipError_t launch_row_dots(const RowDotArgs& a, hipStream_t s);
 hipError_t launch_route(const RouteArgs& a, hipStream_t s);
 hipError_t launch_sparse_rows(const SparseRowsArgs& a, hipStream_t s);
 
+// ---- term lists for large vocabularies (fr_lists.hip) ------------------
+// An index created with list_terms = L keeps each document's terms as a
+// list of at most L ids, laid out [slot/64][j][slot%64] (term j of 64
+// consecutive slots contiguous), with a count per slot, instead of one
+// bitmap per vocabulary term.  A search first materialises bitmaps for the
+// batch's own distinct terms only (the dictionary, sorted; literals are
+// renumbered to dictionary indices on the host), in the layout of the
+// per-term bitmaps: [group][n_dict][16 words].
+constexpr uint32_t kBatchTermsMax = 1024;
+
+struct ListWriteArgs {
+  const uint64_t* off;     // n + 1 offsets into terms
+  const uint32_t* terms;
+  const uint32_t* slots;   // slot of each row, or null -> slot_base + i
+  uint64_t slot_base;
+  uint64_t n;
+  uint32_t* tlist;
+  uint32_t* tcnt;
+  uint32_t L;
+};
+
+struct BatchBitsArgs {
+  const uint32_t* tlist;
+  const uint32_t* tcnt;
+  uint32_t L;
+  uint32_t n_groups;
+  const uint32_t* dict;    // sorted distinct terms of the batch
+  uint32_t n_dict;         // <= kBatchTermsMax
+  uint64_t* bits;          // out: [group][n_dict][16]
+};
+
+hipError_t launch_list_write(const ListWriteArgs& a, hipStream_t s);
+hipError_t launch_batch_bits(const BatchBitsArgs& a, hipStream_t s);
+
 // Launchers (fr_kernels.hip).  Each returns the HIP error of the launch.
 hipError_t launch_tile_rows(const TileRowsArgs& a, hipStream_t s);
 hipError_t launch_terms(const TermArgs& a, hipStream_t s);

@@ -136,6 +136,12 @@ struct Workspace {
   uint32_t* surv = nullptr;    // [q][scap]
   uint32_t* ties = nullptr;    // [q][tcap]
   unsigned long long* qkey = nullptr;   // [q][scap]
+  // term lists: the batch dictionary (device + pinned twin, after the input
+  // block) and the bitmaps of its terms
+  uint32_t* dict = nullptr;
+  uint32_t* h_dict = nullptr;
+  uint64_t* bbits = nullptr;
+  uint32_t n_dict = 0;
   // sparse routing: the sparse queries and their matching rows
   uint32_t* slist = nullptr;
   uint32_t* srows = nullptr;   // [q][rcap]
@@ -169,6 +175,10 @@ struct fr_index {
   // sign codes: bits per document (0: none), quantK = factor * k (at most
   // scap), tie buffer per query, the corpus codes and the encoding table
   uint32_t qbits = 0, qfactor = 0, scap = 0, tcap = 0;
+  // term lists (list_terms > 0) instead of per-term bitmaps
+  uint32_t L = 0, batch_terms = 0;
+  uint32_t* tlist = nullptr;
+  uint32_t* tcnt = nullptr;
   uint64_t* codes = nullptr;
   uint32_t* d_bin_off = nullptr;
   uint32_t* d_bin_dim = nullptr;
@@ -328,6 +338,10 @@ size_t layout_workspace(const fr_index* ix, Workspace& w, uint8_t* base, uint32_
   carve(&w.mw, base, off, (size_t)std::max<uint64_t>(n_groups, 1) * kWords * w.ppad);
   carve(&w.sel_key, base, off, (size_t)qm * ix->rmax);
   carve(&w.sel_slot, base, off, (size_t)qm * ix->rmax);
+  if (ix->L) {
+    carve(&w.dict, base, off, ix->batch_terms);
+    carve(&w.bbits, base, off, (size_t)std::max<uint64_t>(n_groups, 1) * ix->batch_terms * kWords);
+  }
   if (outputs) {
     carve(&w.slist, base, off, qm);
     carve(&w.srows, base, off, (size_t)qm * sparse_cap(ix));
@@ -360,6 +374,7 @@ void layout_host_inputs(Workspace& w, uint32_t* h_in) {
   w.h_co = w.h_k + w.qcap;
   w.h_lo = w.h_co + w.qcap + 1;
   w.h_terms = w.h_lo + w.cmax + 1;
+  w.h_dict = w.h_terms + w.lmax;
 }
 
 }  // namespace
@@ -385,6 +400,40 @@ hipError_t encode_rows(fr_index* ix, const float* rows, uint32_t ld, uint64_t n,
   sa.codes = ix->codes;
   sa.corpus_layout = 1;
   return launch_sign_codes(sa, ix->stream);
+}
+
+// A document's terms into the index: bits of its slot in the per-term
+// bitmaps (set, or cleared for a delete), or, with term lists, its list
+// (a delete leaves the list: the live bit excludes the slot, and a later
+// insert overwrites it).
+hipError_t write_terms(fr_index* ix, const TermArgs& tm) {
+  if (!ix->L) return launch_terms(tm, ix->stream);
+  if (!tm.set) return hipSuccess;
+  ListWriteArgs lw{};
+  lw.off = tm.off;
+  lw.terms = tm.terms;
+  lw.slots = tm.slots;
+  lw.slot_base = tm.slot_base;
+  lw.n = tm.n;
+  lw.tlist = ix->tlist;
+  lw.tcnt = ix->tcnt;
+  lw.L = ix->L;
+  return launch_list_write(lw, ix->stream);
+}
+
+// With term lists, the bitmaps of the batch's dictionary terms, before a
+// search's first mask pass.
+hipError_t batch_bits(fr_index* ix, Workspace& w, uint32_t n_groups, hipStream_t s) {
+  if (!ix->L) return hipSuccess;
+  BatchBitsArgs bb{};
+  bb.tlist = ix->tlist;
+  bb.tcnt = ix->tcnt;
+  bb.L = ix->L;
+  bb.n_groups = n_groups;
+  bb.dict = w.dict;
+  bb.n_dict = w.n_dict;
+  bb.bits = w.bbits;
+  return launch_batch_bits(bb, s);
 }
 
 fr_status wait_all(fr_index* ix) {
@@ -487,7 +536,7 @@ fr_status enqueue_deletes(fr_index* ix, uint64_t m, uint64_t nt) {
   tm.bits = ix->bits;
   tm.vocab = ix->cfg.vocab;
   tm.set = 0;
-  FR_HIP(launch_terms(tm, ix->stream));
+  FR_HIP(write_terms(ix, tm));
   return FR_OK;
 }
 
@@ -525,7 +574,7 @@ fr_status enqueue_inserts(fr_index* ix, uint64_t m, uint64_t nt) {
   tm.bits = ix->bits;
   tm.vocab = ix->cfg.vocab;
   tm.set = 1;
-  FR_HIP(launch_terms(tm, ix->stream));
+  FR_HIP(write_terms(ix, tm));
   LiveArgs la{};
   la.slots = ix->d_uslots;
   la.n = m;
@@ -556,8 +605,12 @@ void compact_terms(fr_index* ix) {
 fr_status check_terms(const fr_index* ix, uint64_t n, const uint64_t* off, const uint32_t* terms) {
   if (n && (!off || (off[n] > off[0] && !terms)))
     return fail(FR_EINVAL, "term_off / terms missing");
-  for (uint64_t i = 0; i < n; ++i)
+  for (uint64_t i = 0; i < n; ++i) {
     if (off[i + 1] < off[i]) return fail(FR_EINVAL, "term_off must be non-decreasing");
+    if (ix->L && off[i + 1] - off[i] > ix->L)
+      return fail(FR_EINVAL, "a document has more terms than list_terms (" +
+                                 std::to_string(ix->L) + ")");
+  }
   for (uint64_t j = n ? off[0] : 0; j < (n ? off[n] : 0); ++j)
     if (terms[j] >= ix->cfg.vocab)
       return fail(FR_EINVAL, "term id " + std::to_string(terms[j]) + " >= vocab");
@@ -634,7 +687,7 @@ fr_status write_docs(fr_index* ix, uint64_t n, const float* emb, const uint32_t*
     tm.bits = ix->bits;
     tm.vocab = ix->cfg.vocab;
     tm.set = 1;
-    FR_HIP(launch_terms(tm, ix->stream));
+    FR_HIP(write_terms(ix, tm));
     LiveArgs la{};
     la.slots = ta.slots;
     la.slot_base = ta.slot_base;
@@ -783,8 +836,8 @@ MaskWordArgs mask_args(const fr_index* ix, Workspace& w, uint32_t n_groups) {
   ma.n_groups = n_groups;
   ma.gpt = std::max<uint32_t>(1, std::min<uint32_t>(16, (uint32_t)(((uint64_t)n_groups * w.qcap) >> 18)));
   ma.live = ix->live;
-  ma.bits = ix->bits;
-  ma.vocab = ix->cfg.vocab;
+  ma.bits = ix->L ? w.bbits : ix->bits;
+  ma.vocab = ix->L ? w.n_dict : ix->cfg.vocab;
   ma.lit = w.lit;
   ma.linfo = w.linfo;
   ma.clause_off = w.clause_off;
@@ -817,6 +870,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
   ta.scale = w.qscale;
   ta.norm = w.qnorm;
   FR_HIP(launch_query_prep(ta, prep_args(ix, w), s));
+  FR_HIP(batch_bits(ix, w, n_groups, s));
   const MaskWordArgs ma = mask_args(ix, w, n_groups);
   FR_HIP(launch_mask_words(ma, s));
 
@@ -948,8 +1002,8 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
   sa.tiles = ix->tiles;
   sa.xscale = ix->xscale;
   sa.live = ix->live;
-  sa.bits = ix->bits;
-  sa.vocab = ix->cfg.vocab;
+  sa.bits = ix->L ? w.bbits : ix->bits;
+  sa.vocab = ix->L ? w.n_dict : ix->cfg.vocab;
   sa.n_groups = n_groups;
   sa.qtiles = w.qtiles;
   sa.qscale = w.qscale;
@@ -1049,6 +1103,7 @@ fr_status enqueue_preselect(fr_index* ix, Workspace& w, hipStream_t s, uint32_t 
   qa.n_bits = ix->qbits;
   qa.codes = w.qcode;
   FR_HIP(launch_sign_codes(qa, s));
+  FR_HIP(batch_bits(ix, w, n_groups, s));
   const MaskWordArgs ma = mask_args(ix, w, n_groups);
   FR_HIP(launch_mask_words(ma, s));
   FR_HIP(launch_fill_u32(w.qhist, 0u, (uint64_t)w.qcap * (ix->qbits + 1), s));
@@ -1215,7 +1270,25 @@ fr_status stage_inputs(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_q,
   std::memcpy(w.h_co, cnf->clause_off, (n_q + 1) * 4);
   if (n_c) std::memcpy(w.h_lo, cnf->literal_off, (n_c + 1) * 4);
   else w.h_lo[0] = 0;
-  if (n_l) std::memcpy(w.h_terms, cnf->terms, n_l * 4);
+  if (ix->L) {
+    // term lists: the batch's distinct terms, sorted, and the literals as
+    // their indices (the bitmaps are built for these terms only)
+    std::vector<uint32_t> u(cnf->terms, cnf->terms + n_l);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    if (u.size() > ix->batch_terms)
+      return fail(FR_EINVAL, "the batch has " + std::to_string(u.size()) +
+                                 " distinct terms, more than batch_terms (" +
+                                 std::to_string(ix->batch_terms) + ")");
+    for (uint32_t i = 0; i < n_l; ++i)
+      w.h_terms[i] = (uint32_t)(std::lower_bound(u.begin(), u.end(), cnf->terms[i]) - u.begin());
+    if (!u.empty()) std::memcpy(w.h_dict, u.data(), u.size() * 4);
+    w.n_dict = (uint32_t)u.size();
+    if (w.n_dict)
+      FR_HIP(hipMemcpyAsync(w.dict, w.h_dict, w.n_dict * 4, hipMemcpyHostToDevice, s));
+  } else if (n_l) {
+    std::memcpy(w.h_terms, cnf->terms, n_l * 4);
+  }
   const size_t words = (size_t)(w.h_terms - w.h_in) + n_l;
   FR_HIP(hipMemcpyAsync(w.in, w.h_in, words * 4, hipMemcpyHostToDevice, s));
   return FR_OK;
@@ -1265,6 +1338,7 @@ fr_status index_shape(fr_index* ix, IndexShape* out) {
   out->max_clauses = ix->cmax;
   out->max_literals = ix->lmax;
   out->n_workspaces = (uint32_t)ix->ws.size();
+  out->batch_terms = ix->batch_terms;
   out->device = ix->cfg.device;
   return FR_OK;
 }
@@ -1279,7 +1353,11 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   if (!cfg || !out) return fail(FR_EINVAL, "null argument");
   *out = nullptr;
   if (cfg->dim < 1 || cfg->dim > 256) return fail(FR_EUNSUPPORTED, "dim must be 1..256");
-  if (cfg->vocab < 1 || cfg->vocab > (1u << 20)) return fail(FR_EINVAL, "vocab must be 1..2^20");
+  if (cfg->list_terms > 4096) return fail(FR_EINVAL, "list_terms must be 0..4096");
+  if (cfg->batch_terms > (uint32_t)kBatchTermsMax)
+    return fail(FR_EINVAL, "batch_terms must be 0..1024");
+  if (cfg->vocab < 1 || cfg->vocab > (cfg->list_terms ? (1u << 31) : (1u << 20)))
+    return fail(FR_EINVAL, "vocab must be 1..2^20 (1..2^31 with list_terms)");
   if (cfg->k_max < 1 || cfg->k_max > (uint32_t)kMaxR) return fail(FR_EINVAL, "k_max must be 1..4096");
   if (cfg->capacity < 1 || cfg->capacity > (1ull << 32) - kGroup)
     return fail(FR_EINVAL, "capacity must be 1..2^32-1024");
@@ -1313,6 +1391,8 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   if (ix->cand_cap < ix->rmax) return fail(FR_EINVAL, "cand_cap must be >= the selection size");
   if (!scan_supported(ix->dt, ix->dpad, 1, 4))
     return fail(FR_EUNSUPPORTED, "no scan kernel for this dtype/dim");
+  ix->L = cfg->list_terms;
+  ix->batch_terms = ix->L ? (cfg->batch_terms ? cfg->batch_terms : (uint32_t)kBatchTermsMax) : 0;
   ix->qbits = cfg->quant_bits;
   if (ix->qbits && ix->qbits != 64 && ix->qbits != 128 && ix->qbits != 256 && ix->qbits != 512)
     return fail(FR_EINVAL, "quant_bits must be 0, 64, 128, 256 or 512");
@@ -1365,7 +1445,12 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   }
   FR_ALLOC(dalloc(&ix->slot_ids, cap, D));
   FR_ALLOC(dalloc(&ix->live, cap / 64, D));
-  FR_ALLOC(dalloc(&ix->bits, cap / kGroup * (uint64_t)cfg->vocab * kWords, D));
+  if (ix->L) {
+    FR_ALLOC(dalloc(&ix->tlist, cap * ix->L, D));
+    FR_ALLOC(dalloc(&ix->tcnt, cap, D));
+  } else {
+    FR_ALLOC(dalloc(&ix->bits, cap / kGroup * (uint64_t)cfg->vocab * kWords, D));
+  }
   FR_ALLOC(dalloc(&ix->norm_max, 1, D));
   FR_ALLOC(dalloc(&ix->d_flag, 1, D));
   ix->stage_rows = std::min<uint64_t>(cap, 1u << 18);
@@ -1378,7 +1463,7 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   FR_ALLOC(halloc(&ix->h_flag, 1, H));
   ix->ustage_rows = std::min<uint64_t>(cap, 1u << 14);
   // any one document fits: its distinct terms number at most the vocabulary
-  ix->ustage_terms = std::max<uint64_t>(ix->ustage_rows * 64, cfg->vocab);
+  ix->ustage_terms = std::max<uint64_t>(ix->ustage_rows * 64, ix->L ? ix->L : cfg->vocab);
   FR_ALLOC(dalloc(&ix->d_urows, ix->ustage_rows * ix->dim, D));
   FR_ALLOC(dalloc(&ix->d_uoff, ix->ustage_rows + 1, D));
   FR_ALLOC(dalloc(&ix->d_uterms, ix->ustage_terms, D));
@@ -1404,7 +1489,7 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   const uint32_t nws = cfg->n_workspaces ? cfg->n_workspaces : 1;
   ix->ws.resize(nws);
   const uint32_t qm = ix->qmax, qpad = round_up(qm, kTile);
-  const size_t n_in = 4 + (size_t)qm + (qm + 1) + (ix->cmax + 1) + ix->lmax;
+  const size_t n_in = 4 + (size_t)qm + (qm + 1) + (ix->cmax + 1) + ix->lmax + ix->batch_terms;
   for (auto& w : ix->ws) {
     const size_t bytes = layout_workspace(ix, w, nullptr, qm, ix->cmax, ix->lmax,
                                           cap / kGroup, ix->cand_cap, true);
@@ -1456,7 +1541,8 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
   if (ix->xscale) FR_HIP(launch_fill_u32((uint32_t*)ix->xscale, 0x3F800000u, cap, ix->stream));
   FR_HIP(launch_fill_u32(ix->slot_ids, 0xFFFFFFFFu, cap, ix->stream));
   FR_HIP(launch_fill_u64(ix->live, 0ull, cap / 64, ix->stream));
-  FR_HIP(launch_fill_u64(ix->bits, 0ull, cap / kGroup * (uint64_t)cfg->vocab * kWords, ix->stream));
+  if (ix->L) FR_HIP(launch_fill_u32(ix->tcnt, 0u, cap, ix->stream));
+  else FR_HIP(launch_fill_u64(ix->bits, 0ull, cap / kGroup * (uint64_t)cfg->vocab * kWords, ix->stream));
   FR_HIP(launch_fill_u32(ix->norm_max, 0u, 1, ix->stream));
   for (auto& w : ix->ws) {
     FR_HIP(launch_fill_u32((uint32_t*)w.qrow, 0u, (size_t)qm * ix->dpad, ix->stream));
@@ -1538,7 +1624,8 @@ fr_status fr_load_corpus(fr_index* ix, uint64_t n, const float* emb, const uint3
   // reset the corpus
   const uint64_t used = std::max<uint64_t>(ix->hwm, 1);
   const uint64_t gused = (used + kGroup - 1) / kGroup;
-  FR_HIP(launch_fill_u64(ix->bits, 0ull, gused * (uint64_t)ix->cfg.vocab * kWords, ix->stream));
+  if (ix->L) FR_HIP(launch_fill_u32(ix->tcnt, 0u, gused * kGroup, ix->stream));
+  else FR_HIP(launch_fill_u64(ix->bits, 0ull, gused * (uint64_t)ix->cfg.vocab * kWords, ix->stream));
   FR_HIP(launch_fill_u64(ix->live, 0ull, ix->cap / 64, ix->stream));
   FR_HIP(launch_fill_u32(ix->slot_ids, 0xFFFFFFFFu, ix->cap, ix->stream));
   FR_HIP(launch_fill_u32(ix->norm_max, 0u, 1, ix->stream));
@@ -1555,15 +1642,16 @@ fr_status fr_load_corpus(fr_index* ix, uint64_t n, const float* emb, const uint3
   ix->id2slot.swap(m);
   for (uint64_t i = 0; i < n; ++i) ix->slot_id[i] = hid[i];
   // with headroom, so that inserts append without moving the arena (a
-  // move copies every list while the index is locked)
-  {
+  // move copies every list while the index is locked); term lists need no
+  // host copy (a delete clears nothing)
+  if (!ix->L) {
     const uint64_t used = n ? term_off[n] - term_off[0] : 0;
     std::vector<uint32_t>().swap(ix->t_arena);
     ix->t_arena.reserve(used + used / 4 + (1u << 22));
     ix->t_arena.assign(n ? terms + term_off[0] : terms, n ? terms + term_off[n] : terms);
   }
   std::fill(ix->t_len.begin(), ix->t_len.end(), 0u);
-  for (uint64_t i = 0; i < n; ++i) {
+  for (uint64_t i = 0; i < n && !ix->L; ++i) {
     ix->t_off[i] = term_off[i] - term_off[0];
     ix->t_len[i] = (uint32_t)(term_off[i + 1] - term_off[i]);
   }
@@ -1688,6 +1776,7 @@ fr_status fr_update_docs(fr_index* ix, uint64_t n_del, const uint32_t* del_ids, 
   for (uint64_t i = 0; i < n_ins; ++i) {
     ix->id2slot[ins_ids[i]] = slots[i];
     ix->slot_id[slots[i]] = ins_ids[i];
+    if (ix->L) continue;
     const uint64_t len = ins_term_off[i + 1] - ins_term_off[i];
     ix->t_off[slots[i]] = ix->t_arena.size();
     ix->t_len[slots[i]] = (uint32_t)len;
@@ -2088,6 +2177,7 @@ fr_status fr_debug_masks(fr_index* ix, const fr_cnf_batch* cnf, uint64_t* out_bi
   if (st != FR_OK) return st;
   const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
   FR_HIP(launch_prep(prep_args(ix, w), ix->stream));
+  FR_HIP(batch_bits(ix, w, n_groups, ix->stream));
   const MaskWordArgs ma = mask_args(ix, w, n_groups);
   FR_HIP(launch_mask_words(ma, ix->stream));
   FR_HIP(hipStreamSynchronize(ix->stream));

@@ -19,6 +19,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_set>
 #include <vector>
 
 #include "fr.h"
@@ -153,6 +154,7 @@ fr_status enqueue_batch(fr_server* sv, Slot& sl, std::vector<uint32_t>& co,
 void dispatch_loop(fr_server* sv) {
   (void)hipSetDevice(sv->sh.device);
   std::vector<uint32_t> co, lo, terms, kk;
+  std::unordered_set<uint32_t> dict;
   for (;;) {
     Slot* sl = nullptr;
     {
@@ -178,13 +180,21 @@ void dispatch_loop(fr_server* sv) {
             lk, until, [&] { return sv->stop || sv->pending.size() >= sv->max_batch; });
       }
       // requests in submission order, within one search's limits (each
-      // request alone fits: fr_server_submit checked it)
+      // request alone fits: fr_server_submit checked it); with term lists
+      // also within the batch's distinct-term limit
       uint32_t nc = 0, nl = 0;
+      dict.clear();
       while (!sv->pending.empty() && sl->reqs.size() < sv->max_batch) {
         const Req& r = sv->pending.front();
         if (!sl->reqs.empty() && (nc + r.clause_len.size() > sv->sh.max_clauses ||
                                   nl + r.n_lits > sv->sh.max_literals))
           break;
+        if (sv->sh.batch_terms) {
+          size_t fresh = 0;
+          for (uint32_t t : r.lits) fresh += !dict.count(t);
+          if (!sl->reqs.empty() && dict.size() + fresh > sv->sh.batch_terms) break;
+          dict.insert(r.lits.begin(), r.lits.end());
+        }
         nc += (uint32_t)r.clause_len.size();
         nl += r.n_lits;
         sl->reqs.push_back(std::move(sv->pending.front()));
@@ -353,6 +363,13 @@ fr_status fr_server_submit(fr_server* sv, uint32_t n, const float* queries,
     if (r.clause_len.size() > sh.max_clauses || r.n_lits > sh.max_literals)
       return set_error(FR_EINVAL, "request " + std::to_string(q) +
                                       " has more clauses or literals than one search takes");
+    if (sh.batch_terms) {
+      std::vector<uint32_t> u(r.lits);
+      std::sort(u.begin(), u.end());
+      if ((size_t)(std::unique(u.begin(), u.end()) - u.begin()) > sh.batch_terms)
+        return set_error(FR_EINVAL, "request " + std::to_string(q) +
+                                        " has more distinct terms than one search takes");
+    }
     r.ids = out_ids + (size_t)q * sh.k_max;
     r.scores = out_scores + (size_t)q * sh.k_max;
     r.count = out_count + q;
