@@ -369,6 +369,12 @@ struct RowDotArgs {
   uint32_t dim;
   unsigned long long* key; // [q][key_stride]: FP32 score key << 32 | slot
   uint32_t key_stride;     // >= stride
+  // optional (null: none): each score into the query's selection histogram
+  // over [hlo, hlo + kNBF / hinvw], as the scan bins its candidates, so that
+  // the exact selection can cut before sorting
+  uint32_t* hist;
+  const float* hlo;
+  const float* hinvw;
 };
 
 // Sparse routing: split the batch (queries 0..n-1, whose masks were just

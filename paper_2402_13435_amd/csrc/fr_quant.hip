@@ -66,12 +66,23 @@ hipError_t launch_sign_codes(const SignArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------- code scans
+// The block's query codes, copied once into LDS (a wavefront then reads
+// each query's words as broadcasts instead of waiting on a scalar load per
+// query).
+template <int W>
+__device__ __forceinline__ void load_query_codes(const QuantArgs& a, uint64_t* s_qc, uint32_t q0,
+                                                 uint32_t nql) {
+  for (uint32_t i = threadIdx.x; i < nql * (uint32_t)W; i += blockDim.x)
+    s_qc[i] = a.qcode[(uint64_t)q0 * W + i];
+}
+
 // The wavefront's 64 documents (one per lane) against each query of the
 // block: `visit(qi, score, matched)` for every query with at least one match
-// among them.  Query codes and mask words are uniform across the wavefront.
+// among them.  Query codes (LDS) and mask words are uniform across the
+// wavefront.
 template <int W, typename Visit>
-__device__ __forceinline__ void scan_slice(const QuantArgs& a, uint32_t sl, uint32_t q0,
-                                           uint32_t nql, int lane, Visit&& visit) {
+__device__ __forceinline__ void scan_slice(const QuantArgs& a, const uint64_t* s_qc, uint32_t sl,
+                                           uint32_t q0, uint32_t nql, int lane, Visit&& visit) {
   uint64_t x[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) x[w] = a.codes[((uint64_t)sl * W + w) * 64u + lane];
@@ -83,7 +94,7 @@ __device__ __forceinline__ void scan_slice(const QuantArgs& a, uint32_t sl, uint
     const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, (int)qi) << 32) |
                        (uint32_t)__builtin_amdgcn_readlane((int)mlo, (int)qi);
     if (m == 0ull) continue;
-    const uint64_t* y = a.qcode + (uint64_t)(q0 + qi) * W;
+    const uint64_t* y = s_qc + qi * W;
     uint32_t sc = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) sc += (uint32_t)__popcll(~(x[w] ^ y[w]));
@@ -94,17 +105,19 @@ __device__ __forceinline__ void scan_slice(const QuantArgs& a, uint32_t sl, uint
 template <int W>
 __global__ __launch_bounds__(256) void k_quant_hist(QuantArgs a) {
   __shared__ uint32_t s_hist[kQuantQB * 513];
+  __shared__ uint64_t s_qc[kQuantQB * 8];
   const uint32_t nq = min(*a.n_dev, a.max_q);
   const uint32_t q0 = blockIdx.y * (uint32_t)kQuantQB;
   if (q0 >= nq) return;
   const uint32_t nql = min((uint32_t)kQuantQB, nq - q0);
   const uint32_t nb1 = a.n_bits + 1u;
   for (uint32_t i = threadIdx.x; i < kQuantQB * nb1; i += blockDim.x) s_hist[i] = 0u;
+  load_query_codes<W>(a, s_qc, q0, nql);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const uint32_t sl1 = min((blockIdx.x + 1u) * a.spb, a.n_slices);
   for (uint32_t sl = blockIdx.x * a.spb + (threadIdx.x >> 6); sl < sl1; sl += 4u)
-    scan_slice<W>(a, sl, q0, nql, lane, [&](uint32_t qi, uint32_t sc, bool hit) {
+    scan_slice<W>(a, s_qc, sl, q0, nql, lane, [&](uint32_t qi, uint32_t sc, bool hit) {
       if (hit) atomicAdd(&s_hist[qi * nb1 + sc], 1u);
     });
   __syncthreads();
@@ -132,19 +145,26 @@ __device__ __forceinline__ void wave_append(bool p, uint32_t* counter, uint32_t*
 
 template <int W>
 __global__ __launch_bounds__(256) void k_quant_collect(QuantArgs a) {
+  __shared__ uint64_t s_qc[kQuantQB * 8];
   const uint32_t nq = min(*a.n_dev, a.max_q);
   const uint32_t q0 = blockIdx.y * (uint32_t)kQuantQB;
   if (q0 >= nq) return;
   const uint32_t nql = min((uint32_t)kQuantQB, nq - q0);
+  load_query_codes<W>(a, s_qc, q0, nql);
+  __syncthreads();
   const int lane = threadIdx.x & 63;
+  // the block's thresholds and flags, lane l holding query q0 + l, read
+  // once: in the query loop they are wave-uniform register reads
+  const uint32_t my_thr = lane < (int)nql ? a.thr[q0 + (uint32_t)lane] : 0u;
+  const uint32_t my_flag = lane < (int)nql ? a.flag[q0 + (uint32_t)lane] : kQuantFail;
   const uint32_t sl1 = min((blockIdx.x + 1u) * a.spb, a.n_slices);
   for (uint32_t sl = blockIdx.x * a.spb + (threadIdx.x >> 6); sl < sl1; sl += 4u) {
     const uint32_t slot = sl * 64u + (uint32_t)lane;
-    scan_slice<W>(a, sl, q0, nql, lane, [&](uint32_t qi, uint32_t sc, bool hit) {
+    scan_slice<W>(a, s_qc, sl, q0, nql, lane, [&](uint32_t qi, uint32_t sc, bool hit) {
       const uint32_t q = q0 + qi;
-      const uint32_t fl = a.flag[q];
+      const uint32_t fl = (uint32_t)__builtin_amdgcn_readlane((int)my_flag, (int)qi);
       if (fl & kQuantFail) return;
-      const uint32_t t = a.thr[q];
+      const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)my_thr, (int)qi);
       const bool all = (fl & kQuantAll) != 0u;
       wave_append(hit && (sc > t || (all && sc == t)), a.cnt + q,
                   a.surv + (uint64_t)q * a.scap, a.scap, slot, lane);

@@ -961,6 +961,9 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
     rd.dim = ix->dim;
     rd.key = w.cand_key;
     rd.key_stride = w.cand_cap;
+    rd.hist = w.hist;
+    rd.hlo = w.hlo;
+    rd.hinvw = w.hinvw;
     FR_HIP(launch_row_dots(rd, s));
     SelectArgs ss = se;
     ss.qlist = w.slist;
@@ -1173,6 +1176,9 @@ fr_status enqueue_preselect(fr_index* ix, Workspace& w, hipStream_t s, uint32_t 
   qd.dim = ix->dim;
   qd.key = w.qkey;
   qd.key_stride = ix->scap;
+  qd.hist = nullptr;   // the selection sorts every survivor (no cut)
+  qd.hlo = nullptr;
+  qd.hinvw = nullptr;
   FR_HIP(launch_row_dots(qd, s));
 
   SelectArgs se{};

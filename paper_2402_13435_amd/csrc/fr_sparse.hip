@@ -87,12 +87,12 @@ hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
 // thread its place after one counter update per wavefront, and the thread
 // writes its word's slots in order.
 __global__ __launch_bounds__(256) void k_sparse_rows(SparseRowsArgs a) {
-  const uint32_t y = blockIdx.y;
-  if (y >= min(*a.n_slist, a.max_q)) return;
-  const uint32_t q = a.slist[y];
+  const uint32_t n_y = min(*a.n_slist, a.max_q);
   const int lane = threadIdx.x & 63;
   const uint32_t w0 = blockIdx.x * a.gpb * (uint32_t)kWords;
   const uint32_t w1 = min((blockIdx.x + 1u) * a.gpb, a.n_groups) * (uint32_t)kWords;
+  for (uint32_t y = blockIdx.y; y < n_y; y += gridDim.y) {
+  const uint32_t q = a.slist[y];
   uint32_t* out = a.rows + (uint64_t)q * a.cap;
   for (uint32_t base = w0; base < w1; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
@@ -116,6 +116,7 @@ __global__ __launch_bounds__(256) void k_sparse_rows(SparseRowsArgs a) {
       ++pos;
     }
   }
+  }
 }
 hipError_t launch_sparse_rows(const SparseRowsArgs& a, hipStream_t s) {
   FR_REQUIRE(a.slist);
@@ -125,8 +126,10 @@ hipError_t launch_sparse_rows(const SparseRowsArgs& a, hipStream_t s) {
   FR_REQUIRE(a.rows);
   if (!a.max_q || !a.n_groups) return hipSuccess;
   if (a.gpb < 1 || a.ppad < a.max_q) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sparse_rows, dim3((a.n_groups + a.gpb - 1) / a.gpb, a.max_q), dim3(256),
-                     0, s, a);
+  // the sparse list's length is known on the device only: a few blocks per
+  // group range loop over it
+  hipLaunchKernelGGL(k_sparse_rows, dim3((a.n_groups + a.gpb - 1) / a.gpb, min(a.max_q, 32u)),
+                     dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -145,19 +148,16 @@ __device__ __forceinline__ float tile_elem(const uint8_t* tiles, uint64_t slot, 
 // (FP32 FMA), then a fixed butterfly sums the lanes.  Blocks of 4
 // wavefronts cover 64 rows of one query (grid.y = query or list position).
 __global__ __launch_bounds__(256) void k_row_dots(RowDotArgs a) {
-  uint32_t q = blockIdx.y;
-  if (a.qlist) {
-    if (q >= min(*a.n_list, a.max_q)) return;
-    q = a.qlist[q];
-  } else if (q >= min(*a.n_dev, a.max_q)) {
-    return;
-  }
-  const uint32_t c = a.cnt[q];
-  if (c > a.stride) return;   // failed query
+  const uint32_t n_y = min(a.qlist ? *a.n_list : *a.n_dev, a.max_q);
   const int lane = threadIdx.x & 63;
+  for (uint32_t y = blockIdx.y; y < n_y; y += gridDim.y) {
+  const uint32_t q = a.qlist ? a.qlist[y] : y;
+  const uint32_t c = a.cnt[q];
+  if (c > a.stride) continue;   // failed query
   const float* qr = a.qrows + (uint64_t)q * a.q_ld;
   const uint32_t* rl = a.rows + (uint64_t)q * a.stride;
   const uint32_t i0 = blockIdx.x * 64u + (threadIdx.x >> 6) * 16u;
+  const float hlo = a.hist ? a.hlo[q] : 0.f, hiw = a.hist ? a.hinvw[q] : 0.f;
   for (uint32_t i = i0; i < min(i0 + 16u, c); ++i) {
     const uint32_t slot = rl[i];
     float p = 0.f;
@@ -170,8 +170,17 @@ __global__ __launch_bounds__(256) void k_row_dots(RowDotArgs a) {
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off);
-    if (lane == 0)
+    if (lane == 0) {
       a.key[(uint64_t)q * a.key_stride + i] = ((unsigned long long)fkey(p) << 32) | slot;
+      if (a.hist) {
+        const float fb = (p - hlo) * hiw;
+        const int bk = fb >= (float)(kNBF - 1) ? kNBF - 1 : (fb > 0.f ? (int)fb : 0);
+        uint32_t* hq = a.hist + (uint64_t)q * kHist;
+        atomicAdd(hq + kNBC + bk, 1u);
+        atomicAdd(hq + (bk >> 4), 1u);
+      }
+    }
+  }
   }
 }
 hipError_t launch_row_dots(const RowDotArgs& a, hipStream_t s) {
@@ -186,7 +195,12 @@ hipError_t launch_row_dots(const RowDotArgs& a, hipStream_t s) {
   if (a.dim > a.dpad || a.dpad % 64u || a.q_ld < a.dim || a.max_cnt > a.stride ||
       a.key_stride < a.stride)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_row_dots, dim3((a.max_cnt + 63) / 64, a.max_q), dim3(256), 0, s, a);
+  if (a.hist) {
+    FR_REQUIRE(a.hlo);
+    FR_REQUIRE(a.hinvw);
+  }
+  hipLaunchKernelGGL(k_row_dots, dim3((a.max_cnt + 63) / 64, min(a.max_q, 64u)), dim3(256), 0, s,
+                     a);
   return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ def test_launchers_guard_pointers():
             ("launch_seed", "SeedArgs", {"xscale", "qscale"}),
             ("launch_route", "RouteArgs", {"kp"}),
             ("launch_sparse_rows", "SparseRowsArgs", set()),
-            ("launch_row_dots", "RowDotArgs", {"qlist", "n_list", "master", "tiles"}),
+            ("launch_row_dots", "RowDotArgs", {"qlist", "n_list", "master", "tiles", "hist"}),
             ("launch_sign_codes", "SignArgs", {"n_dev", "slots"}),
             ("launch_quant_cut", "QuantSelectArgs", {"ties", "surv", "slot_ids"}),
             ("launch_quant_ties", "QuantSelectArgs", {"k", "hist", "thr", "tau", "hinvw",
