@@ -22,6 +22,7 @@ constexpr int kSeedGroupsF32 = 32;
 constexpr int kSeedGroupsLow = 64;
 constexpr int kSeedGroupsMax = 128;
 constexpr int kSeedBins = 2048;      // histogram buckets of the sample's scores
+constexpr uint32_t kSeedTilesPerWave = 2;   // sampled tiles per query block and wavefront
 // starting-threshold sample: two kept scores per 16 documents of a tile
 constexpr int kSeedKeysMax = kSeedGroupsMax * (kGroup / kTile) * 4;
 // Speculative starting rank: with p the share of a query's matches that lie

@@ -426,13 +426,18 @@ hipError_t launch_query_prep(const TileRowsArgs& t, const PrepArgs& a, hipStream
 // run (128 bytes) are read by one coalesced 16-byte load per lane.  A thread
 // block covers 32 queries x gpt groups; the words are stored word-major so
 // that the scan reads one word of consecutive queries from consecutive
-// addresses.
+// addresses.  Blocks go to the XCDs round robin: the blocks of one group
+// range (all its query blocks) are given to the same XCD, so that the
+// bitmap runs the queries share are read from HBM once into that XCD's L2.
 __global__ __launch_bounds__(256) void k_mask_words(MaskWordArgs a) {
   if (a.run_if && *a.run_if == 0u) return;
+  const uint32_t qx_n = (a.max_list + 31u) / 32u;          // query blocks
+  const uint32_t idx = blockIdx.x / kXcds;
+  const uint32_t gy = (idx / qx_n) * kXcds + blockIdx.x % kXcds;   // group range
   const uint32_t part = threadIdx.x & 7u;
-  const uint32_t pos = blockIdx.x * 32u + (threadIdx.x >> 3);
+  const uint32_t pos = (idx % qx_n) * 32u + (threadIdx.x >> 3);
   const uint32_t n = *a.n_list;
-  if (pos >= n || pos >= a.max_list) return;
+  if (pos >= n || pos >= a.max_list || (uint64_t)gy * a.gpt >= a.n_groups) return;
   const uint32_t q = a.qlist[pos];
   const uint32_t info = a.linfo[q];
   const bool empty = (info >> 24) & 1u, has = (info >> 26) & 1u, slow = (info >> 25) & 1u;
@@ -440,7 +445,7 @@ __global__ __launch_bounds__(256) void k_mask_words(MaskWordArgs a) {
   uint32_t tl[kLits];
 #pragma unroll
   for (int i = 0; i < kLits; ++i) tl[i] = a.lit[(uint64_t)q * kLits + i];
-  const uint64_t g0 = (uint64_t)blockIdx.y * a.gpt;
+  const uint64_t g0 = (uint64_t)gy * a.gpt;
   const uint64_t g1 = min(g0 + a.gpt, (uint64_t)a.n_groups);
   unsigned long long cnt = 0;
   // words 2 part and 2 part + 1 of a 16-word run
@@ -514,8 +519,11 @@ hipError_t launch_mask_words(const MaskWordArgs& a, hipStream_t s) {
   FR_REQUIRE(a.nmatch);
   if (a.gpt < 1 || a.ppad < a.max_list || a.ppad % 256u) return hipErrorInvalidValue;
   if (a.max_list == 0 || a.n_groups == 0) return hipSuccess;
-  const dim3 grid((a.max_list + 31u) / 32u, (a.n_groups + a.gpt - 1u) / a.gpt);
-  hipLaunchKernelGGL(k_mask_words, grid, dim3(256), 0, s, a);
+  // query blocks x group ranges, the ranges rounded up to whole XCD rounds
+  const uint64_t gy_n = (a.n_groups + a.gpt - 1u) / a.gpt;
+  const uint64_t blocks = (uint64_t)((a.max_list + 31u) / 32u) * ((gy_n + kXcds - 1) / kXcds) * kXcds;
+  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mask_words, dim3((uint32_t)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -544,6 +552,63 @@ hipError_t launch_zero_work(uint32_t* work, hipStream_t s) {
 // the next group's reads issued before the current group's matrix
 // instructions (scheduling barriers keep that order), so LDS latency
 // overlaps the matrix work.
+// Products of the A chunks x[0 .. G) (chunks j0 .. j0 + G of the tile, in
+// registers) with the matching chunks of every query block.
+template <int DT, int CH, int QB, int G>
+__device__ __forceinline__ void mma_chunks(f32x16 (&acc)[QB], const uint4 (&x)[G], int j0,
+                                           const uint4 (&bq)[QB][CH]) {
+    if constexpr (DT == kF32) {
+      // 32x32x2 FP32: a chunk holds 4 consecutive k values per lane
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int j = j0 + i;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].x), __uint_as_float(bq[b][j].x), acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].y), __uint_as_float(bq[b][j].y), acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].z), __uint_as_float(bq[b][j].z), acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].w), __uint_as_float(bq[b][j].w), acc[b], 0, 0, 0);
+        }
+      }
+    } else if constexpr (DT == kBF16) {
+      // 32x32x16 BF16: one chunk = the 8 k values of one instruction
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int j = j0 + i;
+#pragma unroll
+        for (int b = 0; b < QB; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x[i]),
+                                                            __builtin_bit_cast(bf16x8, bq[b][j]),
+                                                            acc[b], 0, 0, 0);
+      }
+    } else {
+      // 32x32x64 FP8 (E4M3, format code 0 for both operands, no block
+      // scale): two chunks = the 32 k values of one instruction
+#pragma unroll
+      for (int i = 0; i < G; i += 2) {
+        const int j = j0 + i;
+        const i32x8 av = {(int)x[i].x, (int)x[i].y, (int)x[i].z, (int)x[i].w,
+                          (int)x[i + 1].x, (int)x[i + 1].y, (int)x[i + 1].z, (int)x[i + 1].w};
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+          const i32x8 bv = {(int)bq[b][j].x, (int)bq[b][j].y, (int)bq[b][j].z, (int)bq[b][j].w,
+                            (int)bq[b][j + 1].x, (int)bq[b][j + 1].y, (int)bq[b][j + 1].z,
+                            (int)bq[b][j + 1].w};
+          acc[b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[b], 0, 0, 0, 0, 0, 0);
+        }
+      }
+    }
+}
+
+// One tile's A chunks (chunk-major: chunk j of lane l at 1024 j + 16 l)
+// from LDS into registers.
+template <int CH>
+__device__ __forceinline__ void lds_tile(uint4 (&x)[CH], const uint8_t* slot, int lane) {
+  const uint4* p = (const uint4*)slot + lane;
+#pragma unroll
+  for (int j = 0; j < CH; ++j) x[j] = p[j * 64];
+}
+
 template <int DT, int CH, int QB>
 __device__ __forceinline__ void mma_tile(f32x16 (&acc)[QB], const uint8_t* slot,
                                          const uint4 (&bq)[QB][CH], int lane) {
@@ -558,49 +623,7 @@ __device__ __forceinline__ void mma_tile(f32x16 (&acc)[QB], const uint8_t* slot,
 #pragma unroll
     for (int i = 0; i < G; ++i) d[i] = p[(g * G + i) * 64];
   };
-  auto work = [&](int g, const uint4 (&x)[G]) {
-    if constexpr (DT == kF32) {
-      // 32x32x2 FP32: a chunk holds 4 consecutive k values per lane
-#pragma unroll
-      for (int i = 0; i < G; ++i) {
-        const int j = g * G + i;
-#pragma unroll
-        for (int b = 0; b < QB; ++b) {
-          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].x), __uint_as_float(bq[b][j].x), acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].y), __uint_as_float(bq[b][j].y), acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].z), __uint_as_float(bq[b][j].z), acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x[i].w), __uint_as_float(bq[b][j].w), acc[b], 0, 0, 0);
-        }
-      }
-    } else if constexpr (DT == kBF16) {
-      // 32x32x16 BF16: one chunk = the 8 k values of one instruction
-#pragma unroll
-      for (int i = 0; i < G; ++i) {
-        const int j = g * G + i;
-#pragma unroll
-        for (int b = 0; b < QB; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x[i]),
-                                                            __builtin_bit_cast(bf16x8, bq[b][j]),
-                                                            acc[b], 0, 0, 0);
-      }
-    } else {
-      // 32x32x64 FP8 (E4M3, format code 0 for both operands, no block
-      // scale): two chunks = the 32 k values of one instruction
-#pragma unroll
-      for (int i = 0; i < G; i += 2) {
-        const int j = g * G + i;
-        const i32x8 av = {(int)x[i].x, (int)x[i].y, (int)x[i].z, (int)x[i].w,
-                          (int)x[i + 1].x, (int)x[i + 1].y, (int)x[i + 1].z, (int)x[i + 1].w};
-#pragma unroll
-        for (int b = 0; b < QB; ++b) {
-          const i32x8 bv = {(int)bq[b][j].x, (int)bq[b][j].y, (int)bq[b][j].z, (int)bq[b][j].w,
-                            (int)bq[b][j + 1].x, (int)bq[b][j + 1].y, (int)bq[b][j + 1].z,
-                            (int)bq[b][j + 1].w};
-          acc[b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[b], 0, 0, 0, 0, 0, 0);
-        }
-      }
-    }
-  };
+  auto work = [&](int g, const uint4 (&x)[G]) { mma_chunks<DT, CH, QB, G>(acc, x, g * G, bq); };
   load(0, buf[0]);
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
@@ -725,9 +748,9 @@ __device__ __forceinline__ void read_scales(float4 (&xs)[4], const float* sslot,
 
 // Starting thresholds from a sample: the first a.n_groups groups of the
 // corpus.  Step 1 scores every (sampled document, list position) pair with
-// the scan's own tile product (one wavefront per 32-document tile and
-// 32-position query block, the same instruction sequence as the scan, so
-// the scores match the scan's) and keeps, for every 16 documents of a tile
+// the scan's own tile product (one wavefront per kSeedTilesPerWave
+// 32-document tiles and a 32-position query block, the same instruction
+// sequence as the scan, so the scores match the scan's) and keeps, for every 16 documents of a tile
 // (one lane's accumulator rows), the two best matching scores: a subset of
 // the sample's matches.  Step 2 reads two ranks off each query's subset
 // through a histogram of its scores:
@@ -751,40 +774,44 @@ __global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
   const uint32_t n_list = *a.n_list;
   const uint32_t pos0 = blockIdx.y * (uint32_t)kTile;
   const uint32_t ng = a.n_groups;
-  const uint32_t t = blockIdx.x * 4u + (uint32_t)wave;
-  if (pos0 >= n_list || pos0 >= a.max_list || t >= ng * (uint32_t)(kGroup / kTile)) return;
+  const uint32_t n_t = ng * (uint32_t)(kGroup / kTile);
+  const uint32_t t0 = (blockIdx.x * 4u + (uint32_t)wave) * kSeedTilesPerWave;
+  if (pos0 >= n_list || pos0 >= a.max_list || t0 >= n_t) return;
   const uint32_t pos = pos0 + (uint32_t)col;
   const bool qv = pos < n_list && pos < a.max_list;
   const uint32_t q = qv ? a.qlist[pos] : 0u;
+  // the query block's B operand, loaded once for the wavefront's tiles
   uint4 bq[1][CH];
   const uint4* qp = (const uint4*)(a.qtiles + (uint64_t)(q / kTile) * (CH * 1024)) + half * 32 +
                     (q % kTile);
 #pragma unroll
   for (int j = 0; j < CH; ++j) bq[0][j] = qv ? qp[j * 64] : make_uint4(0, 0, 0, 0);
-  f32x16 acc[1];
+  const float qs = DT == kFP8 && qv ? a.qscale[q] : 1.f;
+  for (uint32_t t = t0; t < min(t0 + kSeedTilesPerWave, n_t); ++t) {
+    f32x16 acc[1];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) acc[0][v] = 0.f;
-  mma_tile<DT, CH, 1>(acc, a.tiles + (uint64_t)t * (CH * 1024), bq, lane);
-  if (!qv) return;
-  // predicate bits of the tile's 32 documents for this query (tile t is
-  // tile t % 32 of group t / 32: half of mask word (t % 32) / 2)
-  const uint32_t g = t / (uint32_t)(kGroup / kTile), tg = t % (uint32_t)(kGroup / kTile);
-  const uint64_t mword = a.mw[((uint64_t)g * kWords + (tg >> 1)) * a.ppad + pos];
-  const uint32_t mrow = (uint32_t)(mword >> ((tg & 1u) * 32u)) >> (4 * half);
-  const float qs = DT == kFP8 ? a.qscale[q] : 1.f;
-  // the two best keys among this lane's matching rows (0: none)
-  uint32_t k1 = 0u, k2 = 0u;
+    for (int v = 0; v < 16; ++v) acc[0][v] = 0.f;
+    mma_tile<DT, CH, 1>(acc, a.tiles + (uint64_t)t * (CH * 1024), bq, lane);
+    if (!qv) continue;
+    // predicate bits of the tile's 32 documents for this query (tile t is
+    // tile t % 32 of group t / 32: half of mask word (t % 32) / 2)
+    const uint32_t g = t / (uint32_t)(kGroup / kTile), tg = t % (uint32_t)(kGroup / kTile);
+    const uint64_t mword = a.mw[((uint64_t)g * kWords + (tg >> 1)) * a.ppad + pos];
+    const uint32_t mrow = (uint32_t)(mword >> ((tg & 1u) * 32u)) >> (4 * half);
+    // the two best keys among this lane's matching rows (0: none)
+    uint32_t k1 = 0u, k2 = 0u;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    float sc = acc[0][v];
-    if constexpr (DT == kFP8) sc = (sc * qs) * a.xscale[(uint64_t)t * kTile + acc_row(v, half)];
-    const uint32_t key = ((mrow >> (8 * (v >> 2) + (v & 3))) & 1u) ? fkey(sc) : 0u;
-    const uint32_t lo = min(k1, key);
-    k1 = max(k1, key);
-    k2 = max(k2, lo);
+    for (int v = 0; v < 16; ++v) {
+      float sc = acc[0][v];
+      if constexpr (DT == kFP8) sc = (sc * qs) * a.xscale[(uint64_t)t * kTile + acc_row(v, half)];
+      const uint32_t key = ((mrow >> (8 * (v >> 2) + (v & 3))) & 1u) ? fkey(sc) : 0u;
+      const uint32_t lo = min(k1, key);
+      k1 = max(k1, key);
+      k2 = max(k2, lo);
+    }
+    *(uint2*)(a.skey + (uint64_t)pos * a.row + (uint64_t)t * 4u + 2u * (uint32_t)half) =
+        make_uint2(k1, k2);
   }
-  *(uint2*)(a.skey + (uint64_t)pos * a.row + (uint64_t)t * 4u + 2u * (uint32_t)half) =
-      make_uint2(k1, k2);
 }
 
 // Bucket of a per-query histogram (kSeedBins counters, lane l holding
@@ -933,7 +960,8 @@ hipError_t launch_seed(const SeedArgs& a, int dt, int dpad, hipStream_t s) {
       (uint64_t)a.n_groups * (kGroup / kTile) * 4u > (uint64_t)kSeedKeysMax)
     return hipErrorInvalidValue;
   const uint32_t ng = a.n_groups;
-  const dim3 g1((ng * (kGroup / kTile) + 3u) / 4u, (a.max_list + kTile - 1u) / kTile);
+  const dim3 g1((ng * (kGroup / kTile) + 4u * kSeedTilesPerWave - 1u) / (4u * kSeedTilesPerWave),
+                (a.max_list + kTile - 1u) / kTile);
 #define FR_SEED(D, P)                                                  \
   if (dt == D && dpad == P) {                                          \
     hipLaunchKernelGGL((k_seed_scores<D, P>), g1, dim3(256), 0, s, a); \
@@ -1385,6 +1413,10 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   }
 
   // ------------------------------------------------------------ compute
+  // the wavefront's own entries of the hand-over arrays, addressed from a
+  // scalar copy of its index (a vector copy kept live across the loops is
+  // what the register allocator spills)
+  auto wave_s = [&]() -> int { return __builtin_amdgcn_readfirstlane(wave); };
   constexpr int NQW = 32 * QB;              // queries per wavefront
   // matrix-core B operand and per-query state, block b -> query column col
   uint4 bq[QB][CH];
@@ -1483,16 +1515,28 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       while (lds_get(&s_ready[rs]) != sq) __builtin_amdgcn_s_sleep(1);
       const uint8_t* sp = s_ring + rs * R::SB;
       const uint64_t* smw = (const uint64_t*)(sp + R::MOFF);   // [word][QT]
+      // the lane's query column, worked out again for every slot: kept live
+      // across the whole loop it is the value the register allocator spills
+      // (a scratch reload per slot)
+      uint32_t lid = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+      __asm__ __volatile__("" : "+v"(lid));
+      const int bws = __builtin_amdgcn_readfirstlane(bw);
+      auto slot_j = [&](int b) -> int { return (bws * QB + b) * 32 + (int)(lid & 31u); };
       const uint32_t tg0 = (c * TPS) % (kGroup / kTile);      // first tile, within its group
       const uint64_t tile0 = g0 * (uint64_t)(kGroup / kTile) + (uint64_t)c * TPS;
-      // bit u: tile u of the slot has a match for some query of this wavefront
+      // the slot's mask words of this wavefront's queries (kept in registers
+      // for the epilogues); bit u of act: tile u of the slot has a match for
+      // some query of this wavefront
+      uint64_t mwv[QB][R::WPC];
       uint32_t act = 0;
 #pragma unroll
       for (int wl = 0; wl < R::WPC; ++wl) {
         uint64_t o = 0;
 #pragma unroll
-        for (int b = 0; b < QB; ++b)
-          if (kp[b]) o |= smw[wl * QT + my_j(b)];
+        for (int b = 0; b < QB; ++b) {
+          mwv[b][wl] = kp[b] ? smw[wl * QT + slot_j(b)] : 0ull;
+          o |= mwv[b][wl];
+        }
         if constexpr (TPS == 1) {
           if (__ballot((uint32_t)(o >> ((tg0 & 1u) * 32u)) != 0u)) act = 1u;
         } else {
@@ -1502,28 +1546,46 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       }
       if (act) {
 #pragma unroll
-        for (int b = 0; b < QB; ++b) thr[b] = s_thr[my_j(b)];
+        for (int b = 0; b < QB; ++b) thr[b] = s_thr[slot_j(b)];
       }
       // the staging ring's tail as of now (it only advances, so the room
       // computed from it is a lower bound)
-      const uint32_t tail0 = __atomic_load_n(&s_stail[wave], __ATOMIC_RELAXED);
+      const uint32_t tail0 = __atomic_load_n(&s_stail[wave_s()], __ATOMIC_RELAXED);
+      // bit u: this wavefront scores tile u of the slot
+      uint32_t todo = 0;
+#pragma unroll
+      for (int u = 0; u < TPS; ++u)
+        if (((act >> u) & 1u) && (tg0 + (uint32_t)u) % tstride == tslot) todo |= 1u << u;
+      // BF16/FP8: a whole tile's A operand fits in registers, so the next
+      // tile's is read from LDS while this tile's products and epilogue run
+      constexpr bool kPre = DT != kF32;
+      uint4 abuf[kPre ? CH : 1];
+      if constexpr (kPre) {
+        if (todo) lds_tile<CH>(abuf, sp + __builtin_ctz(todo) * R::TB, lane);
+      }
 #pragma unroll
       for (int u = 0; u < TPS; ++u) {
         const uint32_t t = tg0 + (uint32_t)u;                 // tile within its group
         const int wl = TPS == 1 ? 0 : u / 2;                  // its mask word in the slot
-        if (!((act >> u) & 1u) || t % tstride != tslot) continue;
+        if (!((todo >> u) & 1u)) continue;
         f32x16 accs[QB];
 #pragma unroll
         for (int b = 0; b < QB; ++b)
 #pragma unroll
           for (int v = 0; v < 16; ++v) accs[b][v] = 0.f;
-        mma_tile<DT, CH, QB>(accs, sp + u * R::TB, bq, lane);
+        if constexpr (kPre) {
+          mma_chunks<DT, CH, QB, CH>(accs, abuf, 0, bq);
+          const uint32_t nxt = todo & ~((2u << u) - 1u);
+          if (nxt) lds_tile<CH>(abuf, sp + __builtin_ctz(nxt) * R::TB, lane);
+        } else {
+          mma_tile<DT, CH, QB>(accs, sp + u * R::TB, bq, lane);
+        }
         float4 xs[4];
         if constexpr (DT == kFP8) read_scales(xs, (const float*)(sp + R::SOFF) + u * kTile, lane);
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
           f32x16& acc = accs[b];
-          const uint32_t m32 = (uint32_t)(smw[wl * QT + my_j(b)] >> ((t & 1u) * 32u));
+          const uint32_t m32 = (uint32_t)(mwv[b][wl] >> ((t & 1u) * 32u));
           if constexpr (DT == kFP8) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
@@ -1539,27 +1601,40 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
           // only if it matches and scores at least the threshold, and the
           // candidate step runs only when some row of the wavefront does.
           const uint32_t mrow = m32 >> (4 * half);
-          float mx = -INFINITY;
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const uint32_t sel = (uint32_t)__builtin_amdgcn_sbfe(
                 (int)mrow, 8 * (v >> 2) + (v & 3), 1);
             acc[v] = __uint_as_float((__float_as_uint(acc[v]) & sel) | (0xFF800000u & ~sel));
-            mx = fmaxf(mx, acc[v]);
           }
+          // best of each group of four rows (elements 4g .. 4g + 3)
+          float gm[4];
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            gm[g] = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gm[g] = fmaxf(gm[g], acc[4 * g + i]);
+          }
+          float mx = -INFINITY;
+#pragma unroll
+          for (int g = 0; g < 4; ++g) mx = fmaxf(mx, gm[g]);
           const f32x16& s = acc;
           const float th = fmaxf(thr[b], -FLT_MAX);
           if (__ballot(mx >= th)) {
             {
               // wave-wide compaction: the v-th survivors of all lanes take
               // consecutive staging slots (this wavefront is the only writer
-              // of its buffer, so the count needs no atomic)
+              // of its buffer, so the count needs no atomic); groups of four
+              // rows with no survivor in any lane are passed over at once
               const uint32_t q = qi[b];
-              const int jj = my_j(b);
+              const int jj = slot_j(b);
               const uint32_t room = (uint32_t)SR - (shead - tail0);
               uint32_t base = 0;
 #pragma unroll
-              for (int v = 0; v < 16; ++v) {
+              for (int g = 0; g < 4; ++g) {
+                if (!__ballot(gm[g] >= th)) continue;
+#pragma unroll
+              for (int v = 4 * g; v < 4 * g + 4; ++v) {
                 const bool on = s[v] >= th;
                 const uint64_t bal = __ballot(on);
                 if (bal == 0ull) continue;
@@ -1574,8 +1649,8 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
                   const unsigned long long key =
                       ((unsigned long long)k32 << 32) | (unsigned long long)slot;
                   if (idx < room) {
-                    s_sk[wave][(shead + idx) % SR] = key;
-                    s_sq[wave][(shead + idx) % SR] = (uint8_t)jj;
+                    s_sk[wave_s()][(shead + idx) % SR] = key;
+                    s_sq[wave_s()][(shead + idx) % SR] = (uint8_t)jj;
                   } else {
                     // staging full: append directly
                     const uint32_t pos = atomicAdd(a.cnt + q, 1u);
@@ -1590,18 +1665,19 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
                   }
                 }
               }
+              }
               shead += base < room ? base : room;
             }
           }
         }
       }
       if (lane == 0) {
-        lds_put(&s_shead[wave], shead);
-        lds_put(&s_done[wave], sq + 1u);
+        lds_put(&s_shead[wave_s()], shead);
+        lds_put(&s_done[wave_s()], sq + 1u);
       }
     }
     seq0 += n_s;
-    if (lane == 0) lds_put(&s_fin[wave], item_no);
+    if (lane == 0) lds_put(&s_fin[wave_s()], item_no);
     ++item_no;
     wg_barrier();                                     // item end
   }

@@ -834,7 +834,10 @@ MaskWordArgs mask_args(const fr_index* ix, Workspace& w, uint32_t n_groups) {
   ma.max_list = w.qcap;
   ma.ppad = w.ppad;
   ma.n_groups = n_groups;
-  ma.gpt = std::max<uint32_t>(1, std::min<uint32_t>(16, (uint32_t)(((uint64_t)n_groups * w.qcap) >> 18)));
+  // groups per thread: about eight blocks of 32 of the batch's queries per
+  // compute unit (blocks past the batch exit at once)
+  const uint64_t qblocks = (std::max<uint32_t>(w.h_desc[0], 1u) + 31u) / 32u;
+  ma.gpt = std::max<uint32_t>(1, std::min<uint32_t>(16, (uint32_t)(((uint64_t)n_groups * qblocks) >> 11)));
   ma.live = ix->live;
   ma.bits = ix->L ? w.bbits : ix->bits;
   ma.vocab = ix->L ? w.n_dict : ix->cfg.vocab;
