@@ -126,9 +126,11 @@ typedef struct {
   double   alg_bytes;       /* algorithmic HBM bytes of the scan */
   double   alg_flops;       /* 2 * dim * n_queries * n_slots_scanned */
   float    ms_scan;         /* device time of the first scan pass */
-  float    ms_total;        /* device time from the first scan pass to the last kernel */
+  float    ms_total;        /* device time from the first scan pass to the end of the call's
+                              device work (with host buffers, the result copies included) */
   uint32_t n_sparse;        /* queries the sparse routing took out of the scan */
-  float    ms_call;         /* device time from the call's first kernel to its last */
+  float    ms_call;         /* device time of the whole call, from its input upload to the end
+                              of its device work */
 } fr_search_stats;
 
 /* Create an index on `cfg->device` and reserve all its device memory:
@@ -292,8 +294,8 @@ fr_status fr_stats(fr_index* ix, fr_search_stats* out);
 
 /* Device times of the most recent fr_search calls (at most `max`, oldest
  * first, at most 64 remembered): scan_ms[i] is the first scan pass,
- * total_ms[i] the whole call from the first scan to the last kernel (both
- * measured with HIP events on the call's stream).  `n` receives how many
+ * total_ms[i] from the first scan pass to the end of the call's device work
+ * (both measured with HIP events on the call's stream).  `n` receives how many
  * were written; waits for those calls to finish.  Either array may be
  * NULL. */
 fr_status fr_timings(fr_index* ix, uint32_t max, float* scan_ms, float* total_ms, uint32_t* n);

@@ -148,7 +148,11 @@ struct Workspace {
   bool last_preselect = false;
   uint64_t last_survivors = 0;
   hipEvent_t done = nullptr, e_scan0 = nullptr, e_scan1 = nullptr, e_end = nullptr;
-  hipEvent_t e_start = nullptr;   // first kernel of the call
+  // the event that marks the end of the workspace's last call: its timing
+  // ring's end event for a search (one event record for both purposes),
+  // else `done`
+  hipEvent_t fin = nullptr;
+  hipEvent_t e_start = nullptr;   // recorded before the call's input upload
   // timing ring: scan start / scan end / end of the search, per recent call
   static constexpr int kRing = 64;
   hipEvent_t r0[kRing] = {}, r1[kRing] = {}, r2[kRing] = {}, r3[kRing] = {};
@@ -439,7 +443,7 @@ hipError_t batch_bits(fr_index* ix, Workspace& w, uint32_t n_groups, hipStream_t
 fr_status wait_all(fr_index* ix) {
   for (auto& w : ix->ws) {
     if (w.in_flight) {
-      FR_HIP(hipEventSynchronize(w.done));
+      FR_HIP(hipEventSynchronize(w.fin));
       w.in_flight = false;
     }
   }
@@ -458,8 +462,8 @@ fr_status wait_all(fr_index* ix) {
 fr_status order_after_searches(fr_index* ix) {
   for (auto& w : ix->ws) {
     if (!w.in_flight) continue;
-    if (hipEventQuery(w.done) == hipSuccess) w.in_flight = false;
-    else FR_HIP(hipStreamWaitEvent(ix->stream, w.done, 0));
+    if (hipEventQuery(w.fin) == hipSuccess) w.in_flight = false;
+    else FR_HIP(hipStreamWaitEvent(ix->stream, w.fin, 0));
   }
   if (ix->na_inflight) {
     if (hipEventQuery(ix->na_done) == hipSuccess) ix->na_inflight = false;
@@ -859,7 +863,6 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
   // query rows: the workspace's padded copy (host queries), or the caller's
   // device rows, of which the kernel then writes the padded copy that the
   // FP32 rescoring reads
-  if (timing) FR_HIP(hipEventRecord(w.e_start, s));
   TileRowsArgs ta{};
   const bool in_place = qsrc != w.qrow;
   ta.rows = qsrc;
@@ -1072,7 +1075,6 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
     rs.out_nmatch = o_nmatch;
     FR_HIP(launch_rescore(rs, s));
   }
-  if (timing) FR_HIP(hipEventRecord(w.e_end, s));
   return FR_OK;
 }
 
@@ -1083,7 +1085,6 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
 fr_status enqueue_preselect(fr_index* ix, Workspace& w, hipStream_t s, uint32_t n_groups,
                             uint32_t max_qk, bool timing, const float* qsrc, uint32_t* o_ids,
                             float* o_scores, uint32_t* o_count, unsigned long long* o_nm) {
-  if (timing) FR_HIP(hipEventRecord(w.e_start, s));
   TileRowsArgs ta{};
   const bool in_place = qsrc != w.qrow;
   ta.rows = qsrc;
@@ -1219,7 +1220,6 @@ fr_status enqueue_preselect(fr_index* ix, Workspace& w, hipStream_t s, uint32_t 
   se.nmatch = w.nmatch;
   se.out_nmatch = o_nm;
   FR_HIP(launch_select(se, s));
-  if (timing) FR_HIP(hipEventRecord(w.e_end, s));
   return FR_OK;
 }
 
@@ -1308,7 +1308,7 @@ Workspace* acquire_ws(fr_index* ix, bool nowait, fr_status* st) {
   // prefer a workspace that is already free
   for (size_t i = 0; i < n; ++i) {
     Workspace& w = ix->ws[(ix->next_ws + i) % n];
-    if (!w.in_flight || hipEventQuery(w.done) == hipSuccess) {
+    if (!w.in_flight || hipEventQuery(w.fin) == hipSuccess) {
       w.in_flight = false;
       ix->next_ws = (ix->next_ws + i + 1) % n;
       *st = FR_OK;
@@ -1321,7 +1321,7 @@ Workspace* acquire_ws(fr_index* ix, bool nowait, fr_status* st) {
   }
   Workspace& w = ix->ws[ix->next_ws];
   ix->next_ws = (ix->next_ws + 1) % n;
-  if (hipEventSynchronize(w.done) != hipSuccess) {
+  if (hipEventSynchronize(w.fin) != hipSuccess) {
     ix->failed = true;
     *st = fail(FR_EDEVICE, "hipEventSynchronize failed");
     return nullptr;
@@ -1517,6 +1517,7 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(halloc(&w.h_selcnt, qm, H));
     FR_ALLOC(halloc(&w.h_desc_out, 4, H));
     bool ev_ok = hipEventCreate(&w.done) == hipSuccess;
+    w.fin = w.done;
     for (int i = 0; i < Workspace::kRing && ev_ok; ++i)
       ev_ok = hipEventCreate(&w.r0[i]) == hipSuccess && hipEventCreate(&w.r1[i]) == hipSuccess &&
               hipEventCreate(&w.r2[i]) == hipSuccess && hipEventCreate(&w.r3[i]) == hipSuccess;
@@ -1831,6 +1832,11 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   hipStream_t s = async ? (hipStream_t)stream : ix->stream;
   st = order_after_update(ix, s);
   if (st != FR_OK) return st;
+  // the call's timing slot; its start event goes before the input upload,
+  // next to the previous call's end event (every event record between two
+  // kernels costs the device a few microseconds)
+  ring_slot(ix, *w);
+  FR_HIP(hipEventRecord(w->e_start, s));
   // inputs
   w->h_desc[0] = n_q;
   w->h_desc[1] = n_q;
@@ -1838,7 +1844,11 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   w->h_desc[3] = 0;
   std::memcpy(w->h_k, k, n_q * 4);
   st = stage_inputs(ix, *w, s, n_q, cnf, n_c, n_l);
-  if (st != FR_OK) return st;
+  if (st != FR_OK) {
+    ix->history.pop_back();   // nothing of the call ran
+    w->n_calls -= 1;
+    return st;
+  }
   const size_t qbytes = (size_t)ix->dpad * 4;
   // device queries are read in place by the query tiling kernel
   const float* qsrc = dev ? queries : w->qrow;
@@ -1853,7 +1863,6 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   unsigned long long* o_nm = dev ? (unsigned long long*)out_nmatch : w->out_nmatch;
   const uint32_t n_groups = (uint32_t)((ix->hwm + kGroup - 1) / kGroup);
   const Choice ch = choose(ix, n_q, k, n_groups);
-  ring_slot(ix, *w);
   uint64_t survivors = 0;   // pre-selection: sum over queries of min(quantK, live)
   if (pre) {
     uint32_t max_qk = 0;
@@ -1885,11 +1894,9 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
       FR_HIP(hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0));
       std::memcpy(w->gkey, key, sizeof key);
     }
-    FR_HIP(hipEventRecord(w->e_start, s));
     FR_HIP(hipEventRecord(w->e_scan0, s));
     FR_HIP(hipGraphLaunch(w->gexec, s));
     FR_HIP(hipEventRecord(w->e_scan1, s));
-    FR_HIP(hipEventRecord(w->e_end, s));
   } else {
     st = enqueue_search(ix, *w, s, ch, n_groups, true, qsrc, o_ids, o_scores, o_count, o_nm);
     if (st != FR_OK) return st;
@@ -1901,7 +1908,10 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
     FR_HIP(hipMemcpyAsync(w->h_count, w->out_count, n_q * 4, hipMemcpyDeviceToHost, s));
     FR_HIP(hipMemcpyAsync(w->h_nmatch, w->out_nmatch, n_q * 8, hipMemcpyDeviceToHost, s));
   }
-  FR_HIP(hipEventRecord(w->done, s));
+  // the end of the call's device work: the timing ring's end event, which
+  // the workspace's next user waits for
+  FR_HIP(hipEventRecord(w->e_end, s));
+  w->fin = w->e_end;
   w->in_flight = true;
   // algorithmic bytes / flops of this batch (for statistics)
   {
@@ -1931,7 +1941,7 @@ fr_status fr_search(fr_index* ix, uint32_t n_q, const float* queries, const fr_c
   ix->last_ws = (size_t)(w - ix->ws.data());
   ix->have_last = true;
   if (async) return FR_OK;
-  FR_HIP(hipEventSynchronize(w->done));
+  FR_HIP(hipEventSynchronize(w->fin));
   w->in_flight = false;
   bool failed_q = false;
   const uint32_t* cnts = w->h_count;
@@ -2093,7 +2103,7 @@ fr_status fr_stats(fr_index* ix, fr_search_stats* out) {
   std::lock_guard<std::mutex> lk(ix->mu);
   if (!ix->have_last) return fail(FR_EINVAL, "no search yet");
   Workspace& w = ix->ws[ix->last_ws];
-  if (hipEventSynchronize(w.done) != hipSuccess) return fail(FR_EDEVICE, "event");
+  if (hipEventSynchronize(w.fin) != hipSuccess) return fail(FR_EDEVICE, "event");
   // per-query counters of that search, still in its workspace (read here
   // rather than copied back by every search)
   if (hipMemcpy(w.h_cnt, w.cnt, w.last_nq * 4, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -2212,7 +2222,7 @@ fr_status fr_debug_candidates(fr_index* ix, uint32_t n_q, uint32_t* out_ids, flo
   if (!ix->have_last) return fail(FR_EINVAL, "no search yet");
   Workspace& w = ix->ws[ix->last_ws];
   if (n_q > w.last_nq) return fail(FR_EINVAL, "n_q exceeds the last batch");
-  FR_HIP(hipEventSynchronize(w.done));
+  FR_HIP(hipEventSynchronize(w.fin));
   const size_t R = ix->rmax;
   std::vector<unsigned long long> keys((size_t)n_q * R);
   std::vector<uint32_t> cnt(n_q);
