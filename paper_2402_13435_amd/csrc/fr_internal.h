@@ -208,7 +208,7 @@ struct ScanArgs {
   unsigned long long* cand_key;  // [q][cap]: score key << 32 | slot
   uint32_t cap;
   uint32_t* work;
-  uint32_t gpi;            // groups per work item
+  uint32_t tpi;            // tiles per work item (a multiple of 4)
   const uint64_t* mw;      // predicate masks of the pass (see MaskWordArgs)
   uint32_t ppad;
   uint32_t strategy;       // kStrat* bits

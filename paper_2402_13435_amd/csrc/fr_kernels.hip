@@ -1046,7 +1046,6 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   using R = Ring<DT, DPAD, QT>;
   constexpr int CH = R::CH;                 // 16-byte chunks per lane per tile
   constexpr int TPS = R::TPS;               // tiles per ring slot
-  constexpr int SPG = (kGroup / kTile) / TPS;   // slots per group
   constexpr int PD = R::PD;                 // slots in flight
   constexpr int NS = R::NS;                 // ring slots
   constexpr int SR = NW > 4 ? 256 : 512;    // staging ring entries per wavefront
@@ -1086,14 +1085,16 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
   const uint32_t xcd = blockIdx.x % kXcds;
   const uint32_t n_list = *a.n_list;
   const uint32_t n_qtiles = (n_list + QT - 1) / QT;
-  const uint32_t n_chunks = (a.n_groups + a.gpi - 1) / a.gpi;
+  const uint64_t n_tiles = (uint64_t)a.n_groups * (kGroup / kTile);
+  const uint32_t n_chunks = (uint32_t)((n_tiles + a.tpi - 1) / a.tpi);
   const uint32_t my_chunks = n_chunks > xcd ? (n_chunks - xcd + kXcds - 1) / kXcds : 0u;
   const uint32_t my_items = my_chunks * n_qtiles;
-  // the item's groups and tile count (identical in every wavefront)
-  auto item_range = [&](uint32_t item, uint64_t& g0, uint64_t& g1) {
+  // the item's tiles [t0, t1) (identical in every wavefront; t0 and the
+  // count are multiples of 4, so of TPS)
+  auto item_range = [&](uint32_t item, uint64_t& t0, uint64_t& t1) {
     const uint32_t chunk = (item / n_qtiles) * kXcds + xcd;
-    g0 = (uint64_t)chunk * a.gpi;
-    g1 = min(g0 + a.gpi, (uint64_t)a.n_groups);
+    t0 = (uint64_t)chunk * a.tpi;
+    t1 = min(t0 + a.tpi, n_tiles);
   };
   auto wave_sync = [&]() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1125,22 +1126,22 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform
       wg_barrier();
       if (item >= my_items) break;
-      uint64_t g0, g1;
-      item_range(item, g0, g1);
-      const uint32_t n_s = (uint32_t)(g1 - g0) * SPG;
+      uint64_t t0, t1;
+      item_range(item, t0, t1);
+      const uint32_t n_s = (uint32_t)((t1 - t0) / TPS);
       const uint32_t qt = item % n_qtiles;
-      // slot load c: tiles c*TPS .. of the item, mask words (c*TPS)/2 ..
+      // slot load c: tiles t0 + c*TPS .. of the item and their mask words
+      // (word w of group g, 64 documents, is word g*kWords + w = tile / 2 of
+      // the pass)
       auto dma_slot = [&](uint32_t c, uint8_t* sp) {
-        const uint64_t tile = g0 * (uint64_t)(kGroup / kTile) + (uint64_t)c * TPS;
+        const uint64_t tile = t0 + (uint64_t)c * TPS;
 #pragma unroll
         for (int u = 0; u < TPS; ++u)
           dma_tile<DT, CH>(a.tiles, a.xscale, tile + u, sp + u * R::TB,
                            (float*)(sp + R::SOFF) + u * kTile, lane);
-        const uint64_t g = g0 + (c * TPS) / (kGroup / kTile);
-        const uint32_t w0 = ((c * TPS) % (kGroup / kTile)) / 2;
 #pragma unroll
         for (int wl = 0; wl < R::WPC; ++wl) {
-          const uint64_t* src = a.mw + (g * kWords + w0 + wl) * a.ppad + (uint64_t)qt * QT + 2u * lane;
+          const uint64_t* src = a.mw + (tile / 2 + wl) * a.ppad + (uint64_t)qt * QT + 2u * lane;
 #pragma unroll
           for (int k = 0; k < R::LM; ++k)
             __builtin_amdgcn_global_load_lds(
@@ -1496,8 +1497,8 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     wg_barrier();
     if (item >= my_items) break;
     const uint32_t qt = item % n_qtiles;
-    uint64_t g0, g1;
-    item_range(item, g0, g1);
+    uint64_t t0, t1;
+    item_range(item, t0, t1);
 
     if (qt != cur_qt) {
       cur_qt = qt;
@@ -1505,7 +1506,7 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
     }
     wg_barrier();                                     // set-up
 
-    const uint32_t n_s = (uint32_t)(g1 - g0) * SPG;
+    const uint32_t n_s = (uint32_t)((t1 - t0) / TPS);
 #pragma unroll 1
     for (uint32_t c = 0; c < n_s; ++c) {
       // one step per ring slot: wait until the loader has published it,
@@ -1522,8 +1523,8 @@ __global__ __launch_bounds__((NW + 2) * 64) void k_scan(ScanArgs a) {
       __asm__ __volatile__("" : "+v"(lid));
       const int bws = __builtin_amdgcn_readfirstlane(bw);
       auto slot_j = [&](int b) -> int { return (bws * QB + b) * 32 + (int)(lid & 31u); };
-      const uint32_t tg0 = (c * TPS) % (kGroup / kTile);      // first tile, within its group
-      const uint64_t tile0 = g0 * (uint64_t)(kGroup / kTile) + (uint64_t)c * TPS;
+      const uint64_t tile0 = t0 + (uint64_t)c * TPS;            // the slot's first tile
+      const uint32_t tg0 = (uint32_t)(tile0 % (kGroup / kTile));   // ... within its group
       // the slot's mask words of this wavefront's queries (kept in registers
       // for the epilogues); bit u of act: tile u of the slot has a match for
       // some query of this wavefront
@@ -1722,7 +1723,7 @@ hipError_t launch_scan(const ScanArgs& a, int dt, int dpad, int qb, int nw, int 
     FR_REQUIRE(a.xscale);
     FR_REQUIRE(a.qscale);
   }
-  if (a.gpi < 1 || n_wg < 1) return hipErrorInvalidValue;
+  if (a.tpi < 4 || a.tpi % 4 || n_wg < 1) return hipErrorInvalidValue;
   // the loader copies whole query tiles (128 or 256 positions) of mask words
   if (a.ppad < 256u || a.ppad % 256u) return hipErrorInvalidValue;
 #define FR_LAUNCH(D, P, Q, W)                                                          \

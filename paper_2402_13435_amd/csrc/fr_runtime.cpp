@@ -857,6 +857,28 @@ MaskWordArgs mask_args(const fr_index* ix, Workspace& w, uint32_t n_groups) {
   return ma;
 }
 
+// Tiles per scan work item: the chosen groups per item, unless the batch's
+// items all fit in one round of workgroups; then the corpus tiles are spread
+// evenly over the workgroups of each query tile (whole groups would leave up
+// to a group's worth of work per workgroup idle: 1M documents are 977 groups
+// for 256 workgroups).  Rounded up to a multiple of 4, the largest number of
+// tiles per ring slot.
+uint32_t scan_tiles_per_item(const fr_index* ix, const Workspace& w, const Choice& ch,
+                             uint32_t n_groups) {
+  const uint64_t n_tiles = (uint64_t)n_groups * (kGroup / kTile);
+  const uint64_t per_item = (uint64_t)std::max(ch.gpi, 1) * (kGroup / kTile);
+  const uint64_t qt = (std::max<uint32_t>(w.h_desc[0], 1u) + 32u * ch.qb * ch.nw - 1) /
+                      (32u * ch.qb * ch.nw);
+  const uint64_t items = (n_tiles + per_item - 1) / per_item * qt;
+  uint64_t tpi = per_item;
+  if (items <= (uint64_t)ix->n_wg && qt <= (uint64_t)ix->n_wg) {
+    const uint64_t wgs = (uint64_t)ix->n_wg / qt;
+    tpi = std::min(per_item, (n_tiles + wgs - 1) / wgs);
+  }
+  tpi = (tpi + 3) / 4 * 4;
+  return (uint32_t)std::max<uint64_t>(tpi, 4);
+}
+
 fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice& ch,
                          uint32_t n_groups, bool timing, const float* qsrc, uint32_t* o_ids,
                          float* o_scores, uint32_t* o_count, unsigned long long* o_nmatch) {
@@ -1028,7 +1050,7 @@ fr_status enqueue_search(fr_index* ix, Workspace& w, hipStream_t s, const Choice
   sa.cand_key = w.cand_key;
   sa.cap = w.cand_cap;
   sa.work = w.work;
-  sa.gpi = (uint32_t)ch.gpi;
+  sa.tpi = scan_tiles_per_item(ix, w, ch, n_groups);
   sa.strategy = ch.strat;
   sa.mw = w.mw;
   sa.ppad = ma.ppad;
