@@ -409,7 +409,9 @@ fr_status fr_debug_candidates(fr_index* ix, uint32_t n_q, uint32_t* out_ids,
 /* Scan tiling: `query_blocks` blocks of 32 queries per wavefront (1, 2 or
  * 4) and `waves` wavefronts per workgroup (4 or 8), so one pass over a
  * 1024-document group serves 32*query_blocks*waves queries; and
- * `groups_per_item` groups per work item.  Zeros restore the per-batch
+ * `groups_per_item` groups per work item, used when a batch has more than
+ * 32 query tiles (below that the scan cuts the corpus into equal tile
+ * ranges, one item per workgroup).  Zeros restore the per-batch
  * defaults.  FR_EUNSUPPORTED if this build has no such scan kernel for the
  * index's dtype and dimension.  Used by the autotuner and by tests. */
 fr_status fr_set_tiling(fr_index* ix, uint32_t query_blocks, uint32_t waves,

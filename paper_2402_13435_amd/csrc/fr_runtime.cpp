@@ -857,23 +857,25 @@ MaskWordArgs mask_args(const fr_index* ix, Workspace& w, uint32_t n_groups) {
   return ma;
 }
 
-// Tiles per scan work item: the chosen groups per item, unless the batch's
-// items all fit in one round of workgroups; then the corpus tiles are spread
-// evenly over the workgroups of each query tile (whole groups would leave up
-// to a group's worth of work per workgroup idle: 1M documents are 977 groups
-// for 256 workgroups).  Rounded up to a multiple of 4, the largest number of
-// tiles per ring slot.
+// Tiles per scan work item.  Work items are (tile range, query tile) pairs
+// taken from per-XCD queues, the query tiles of one range together on one
+// XCD.  When each XCD's workgroups can hold whole ranges for all query tiles
+// at once, the corpus is cut into as many equal ranges as fit, so that every
+// workgroup takes one item of the same size: whole 1024-document groups (the
+// tuned groups per item) would leave up to a group's worth of work per
+// workgroup idle at the end (1M documents are 977 groups for 256
+// workgroups).  Otherwise the tuned groups per item.  A multiple of 4, the
+// largest number of tiles per ring slot.
 uint32_t scan_tiles_per_item(const fr_index* ix, const Workspace& w, const Choice& ch,
                              uint32_t n_groups) {
   const uint64_t n_tiles = (uint64_t)n_groups * (kGroup / kTile);
-  const uint64_t per_item = (uint64_t)std::max(ch.gpi, 1) * (kGroup / kTile);
   const uint64_t qt = (std::max<uint32_t>(w.h_desc[0], 1u) + 32u * ch.qb * ch.nw - 1) /
                       (32u * ch.qb * ch.nw);
-  const uint64_t items = (n_tiles + per_item - 1) / per_item * qt;
-  uint64_t tpi = per_item;
-  if (items <= (uint64_t)ix->n_wg && qt <= (uint64_t)ix->n_wg) {
-    const uint64_t wgs = (uint64_t)ix->n_wg / qt;
-    tpi = std::min(per_item, (n_tiles + wgs - 1) / wgs);
+  const uint64_t wg_xcd = std::max<uint64_t>((uint64_t)ix->n_wg / kXcds, 1);
+  uint64_t tpi = (uint64_t)std::max(ch.gpi, 1) * (kGroup / kTile);
+  if (qt <= wg_xcd) {
+    const uint64_t ranges = (uint64_t)kXcds * (wg_xcd / qt);
+    tpi = (n_tiles + ranges - 1) / ranges;
   }
   tpi = (tpi + 3) / 4 * 4;
   return (uint32_t)std::max<uint64_t>(tpi, 4);
