@@ -1772,8 +1772,41 @@ __device__ __forceinline__ int pow2_at_least(int n) {
 // its candidates overflowed the buffer; why 2: its speculative starting
 // threshold proved above the K'-th best).  Set it up for the second pass
 // and append it to that pass's list.  Called by the whole workgroup.
-__device__ void select_rerun(const SelectArgs& a, uint32_t q, uint32_t why) {
+// Fine bucket (coarse * 16 + fine) where the count from the top of a query's
+// histogram (kNBC coarse counters, then 16 fine ones per coarse bucket) first
+// reaches kp; -1 when the histogram holds fewer.  Where the coarse and fine
+// counts disagree, the coarse bucket's lowest fine bucket (the safe side).
+__device__ int hist_cut(const uint32_t* h, uint32_t kp) {
+  uint32_t suffix = 0;
+  int bstar = -1;
+  for (int c = kNBC - 1; c >= 0 && bstar < 0; --c) {
+    if (suffix + h[c] < kp) {
+      suffix += h[c];
+      continue;
+    }
+    for (int f = 15; f >= 0; --f) {
+      suffix += h[kNBC + c * 16 + f];
+      if (suffix >= kp) {
+        bstar = c * 16 + f;
+        break;
+      }
+    }
+    if (bstar < 0) bstar = c * 16;
+  }
+  return bstar;
+}
+
+// The query's histogram copied to LDS by the whole block (one round of
+// loads instead of a serial chain of them in one thread).
+__device__ void load_hist(const SelectArgs& a, uint32_t q, uint32_t* s_h) {
+  const uint32_t* h = a.hist + (uint64_t)q * kHist;
+  for (int i = threadIdx.x; i < kHist; i += blockDim.x) s_h[i] = h[i];
+  __syncthreads();
+}
+
+__device__ void select_rerun(const SelectArgs& a, uint32_t q, uint32_t why, uint32_t* s_h) {
   uint32_t* h = a.hist + (uint64_t)q * kHist;
+  if (why != 2u) load_hist(a, q, s_h);
   if (threadIdx.x == 0) {
     float lo, hi;
     if (why == 2u) {
@@ -1790,22 +1823,7 @@ __device__ void select_rerun(const SelectArgs& a, uint32_t q, uint32_t why) {
       // rule and one-bucket margin as the scan's refresh
       const uint32_t kp = a.kp[q];
       const float lo0 = a.hlo[q], iw0 = a.hinvw[q];
-      uint32_t suffix = 0;
-      int bstar = -1;
-      for (int c = kNBC - 1; c >= 0 && bstar < 0; --c) {
-        if (suffix + h[c] < kp) {
-          suffix += h[c];
-          continue;
-        }
-        for (int f = 15; f >= 0; --f) {
-          suffix += h[kNBC + c * 16 + f];
-          if (suffix >= kp) {
-            bstar = c * 16 + f;
-            break;
-          }
-        }
-        if (bstar < 0) bstar = c * 16;   // coarse and fine counts disagree: stay safe
-      }
+      const int bstar = hist_cut(s_h, kp);
       if (kp && bstar >= 2 && iw0 > 0.f) {
         const uint32_t nk = fkey(lo0 + (float)(bstar - 1) / iw0);
         if (nk > a.tau[q]) a.tau[q] = nk;
@@ -1834,6 +1852,7 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
   __shared__ unsigned long long s_key[kSelCap];
   __shared__ uint32_t s_slot[kSelCap];
   __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_h[kHist];
   __shared__ uint32_t s_n, s_digit, s_rank;
   const uint32_t pos = blockIdx.x;
   // the first pass's scan is over: its work counters serve the second one
@@ -1846,7 +1865,7 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     // Candidates were dropped: scan the query again, or, if this was the
     // second pass, mark it failed (count 0xFFFFFFFF, no ids).
     if (!a.final_pass) {
-      select_rerun(a, q, 1u);
+      select_rerun(a, q, 1u, s_h);
       return;
     }
     if (threadIdx.x == 0) {
@@ -1869,7 +1888,7 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     // The speculative starting threshold was above the K'-th best match
     // (fewer candidates than min(K', matches) reached it): scan again from
     // the safe one.
-    select_rerun(a, q, 2u);
+    select_rerun(a, q, 2u, s_h);
     return;
   }
   // Cut before sorting: the query's histogram counts exactly this pass's
@@ -1878,26 +1897,11 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
   // (the same bucket rule as the scan's threshold refresh); candidates below
   // max(tau, that edge) cannot be selected.
   __shared__ uint32_t s_tau;
+  load_hist(a, q, s_h);
   if (threadIdx.x == 0) {
     uint32_t t = a.tau[q];
-    const uint32_t* h = a.hist + (uint64_t)q * kHist;
     const float lo0 = a.hlo[q], iw0 = a.hinvw[q];
-    uint32_t suffix = 0;
-    int bstar = -1;
-    for (int cb = kNBC - 1; cb >= 0 && bstar < 0; --cb) {
-      if (suffix + h[cb] < kp) {
-        suffix += h[cb];
-        continue;
-      }
-      for (int f = 15; f >= 0; --f) {
-        suffix += h[kNBC + cb * 16 + f];
-        if (suffix >= kp) {
-          bstar = cb * 16 + f;
-          break;
-        }
-      }
-      if (bstar < 0) bstar = cb * 16;   // coarse and fine counts disagree: stay safe
-    }
+    const int bstar = hist_cut(s_h, kp);
     if (kp && bstar >= 2 && iw0 > 0.f) t = max(t, fkey(lo0 + (float)(bstar - 1) / iw0));
     s_tau = t;
   }
