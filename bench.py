@@ -237,13 +237,15 @@ def scan_roofline(c, dtype: str, n_q: int, stats, scan_ms: float) -> dict:
     """The scan kernel against both roofs: its algorithmic bytes (each live
     document's stored row once: dpad x element bytes, + 4 for the FP8 row
     scale; one bit per document for each term the batch references; the live
-    bits) and its dense flops 2 d Q N, each per second against the HBM peak
-    and the matrix peak of its dtype; `bound` names the larger fraction."""
+    bits) and its dense flops 2 d Q N over the Q queries it scanned (those
+    sparse routing took out are scored by row gathers instead), each per
+    second against the HBM peak and the matrix peak of its dtype; `bound`
+    names the larger fraction."""
     dpad = (c.cfg.dim + 63) // 64 * 64
     per_doc = dpad * {"f32": 4, "bf16": 2, "fp8": 1}[dtype] + (4 if dtype == "fp8" else 0)
     n = stats.n_live
     alg_bytes = n * per_doc + n * stats.n_terms_batch / 8.0 + n / 8.0
-    flops = 2.0 * c.cfg.dim * n_q * n
+    flops = 2.0 * c.cfg.dim * max(n_q - stats.n_sparse, 0) * n
     t = scan_ms * 1e-3
     gbs = alg_bytes / t / 1e9
     tfs = flops / t / 1e12
@@ -306,7 +308,7 @@ def precision_report(o, qb, res, ids, scores, counts, k_of):
     return {"recall": round(rec, 5), "queries": len(got) - skipped, "max_score_err": err}
 
 
-def timed_search(torch, ix, qb, k, steps, warmup, graph=False, preselect=False):
+def timed_search(torch, ix, qb, k, steps, warmup, graph=False, preselect=False, prewarm_s=0.0):
     from paper_2402_13435_amd import SearchResult
     dev = torch.device("cuda:0")
     q = torch.from_numpy(qb.emb).to(dev)
@@ -316,6 +318,9 @@ def timed_search(torch, ix, qb, k, steps, warmup, graph=False, preselect=False):
                        torch.empty(n_q, dtype=torch.int32, device=dev),
                        torch.empty(n_q, dtype=torch.int64, device=dev))
     stream = torch.cuda.Stream()   # searches are asynchronous on their own stream
+    t_pre = time.perf_counter()
+    while time.perf_counter() - t_pre < prewarm_s:
+        ix.search(q, qb, k, out=out, stream=stream, graph=graph, preselect=preselect)
     for _ in range(warmup):
         ix.search(q, qb, k, out=out, stream=stream, graph=graph, preselect=preselect)
     torch.cuda.synchronize()
@@ -375,6 +380,7 @@ def precision_leg(args, torch, n_docs: int = 0):
         f = {"qps": round(t["qps"], 1), "scan_ms": round(t["scan_ms"], 3),
              "search_ms_device": round(t["total_ms"], 3), "tiling": list(til),
              "candidates_per_query": round(st.candidates / qb.n, 1), "rescore_r": r,
+             "routed_queries": int(st.n_sparse),
              "failed_queries": int(np.sum(t["count"] == 0xFFFFFFFF)),
              "roofline": scan_roofline(c, dt, qb.n, st, t["scan_ms"])}
         f.update(precision_report(o, qb, res, t["ids"], t["scores"], t["count"], lambda q: k))
@@ -440,7 +446,10 @@ def bench_qsweep(args, torch):
     """Roofline curve of the scan: the FP32 workload's corpus (1M x 128,
     vocab 4,096) searched with batches of 1 .. 1,024 queries in FP32, BF16
     and FP8 (R=128); per point the scan's algorithmic bytes and flops per
-    second against the HBM and matrix peaks of its dtype, and which binds."""
+    second against the HBM and matrix peaks of its dtype, and which binds.
+    The tiling and strategy are autotuned per point with sparse routing left
+    out (the sweep characterises the scan); each point runs at least 40
+    timed searches after 0.2 s of untimed ones."""
     import datagen
     from paper_2402_13435_amd import Index
     cfg = datagen.CONFIGS["fp32"]
@@ -462,7 +471,8 @@ def bench_qsweep(args, torch):
             qb = big.subset(list(range(q)))
             if pre:
                 # sign codes, quantK = 200 K, FP32 scores of the survivors
-                t = timed_search(torch, ix, qb, 100, args.steps, args.warmup, preselect=True)
+                t = timed_search(torch, ix, qb, 100, max(args.steps, 40), args.warmup,
+                                 preselect=True, prewarm_s=0.2)
                 res = (None, None, t["count"], t["n_match"])
                 rf = preselect_roofline(c, 512, res, t["stats"], t["scan_ms"])
                 points.append({"dtype": dt, "q": q, "qps": round(t["qps"], 1),
@@ -474,8 +484,13 @@ def bench_qsweep(args, torch):
                                "survivors_per_query": round(t["stats"].candidates / q, 1)})
                 log(json.dumps(points[-1]))
                 continue
-            til = ix.autotune(qb.emb, qb, 100)
-            t = timed_search(torch, ix, qb, 100, args.steps, args.warmup)
+            from paper_2402_13435_amd.binding import FR_STRAT_SPARSE_MASK
+            ix.set_strategy(0, pinned=False)      # the tuning table's choice per point
+            til = list(ix.autotune(qb.emb, qb, 100))
+            if til[3] & FR_STRAT_SPARSE_MASK:
+                til[3] &= ~FR_STRAT_SPARSE_MASK
+                ix.set_strategy(til[3], pinned=True)
+            t = timed_search(torch, ix, qb, 100, max(args.steps, 40), args.warmup, prewarm_s=0.2)
             st = t["stats"]
             scan_s = t["scan_ms"] * 1e-3
             gbs = st.alg_bytes / scan_s / 1e9
@@ -774,7 +789,7 @@ def main() -> int:
     qps = n_q * args.steps / f32["elapsed"]
     st = f32["stats"]
     scan_avg_ms = float(np.mean(f32["scan_ms"]))
-    flops = 2.0 * c.cfg.dim * n_q * st.n_live
+    flops = 2.0 * c.cfg.dim * (n_q - st.n_sparse) * st.n_live
     achieved_tf = flops / (scan_avg_ms * 1e-3) / 1e12
     alg_bytes_scan = st.alg_bytes
     line = {

@@ -26,6 +26,9 @@ FR_DEVICE_PTRS, FR_NOWAIT, FR_GRAPH, FR_ASYNC, FR_PRESELECT = 1, 2, 4, 8, 16
 FR_STRAT_NO_SPECULATION, FR_STRAT_NO_REFRESH = 1, 2
 
 
+FR_STRAT_SPARSE_MASK = 0xF0
+
+
 def FR_STRAT_SPARSE(level: int) -> int:
     """Sparse routing level 1..7 (see include/fr.h)."""
     return int(level) << 4
