@@ -1542,9 +1542,14 @@ fr_status fr_create(const fr_config* cfg, fr_index** out) {
     FR_ALLOC(halloc(&w.h_desc_out, 4, H));
     bool ev_ok = hipEventCreate(&w.done) == hipSuccess;
     w.fin = w.done;
+    // the call's start and the scan's bracket only time the device: no
+    // system-scope fence (cache write-back and invalidation between the
+    // kernels); the end event is also the host's completion event and keeps it
     for (int i = 0; i < Workspace::kRing && ev_ok; ++i)
-      ev_ok = hipEventCreate(&w.r0[i]) == hipSuccess && hipEventCreate(&w.r1[i]) == hipSuccess &&
-              hipEventCreate(&w.r2[i]) == hipSuccess && hipEventCreate(&w.r3[i]) == hipSuccess;
+      ev_ok = hipEventCreateWithFlags(&w.r0[i], hipEventDisableSystemFence) == hipSuccess &&
+              hipEventCreateWithFlags(&w.r1[i], hipEventDisableSystemFence) == hipSuccess &&
+              hipEventCreate(&w.r2[i]) == hipSuccess &&
+              hipEventCreateWithFlags(&w.r3[i], hipEventDisableSystemFence) == hipSuccess;
     if (!ev_ok) {
       cleanup();
       return fail(FR_EDEVICE, "hipEventCreate failed");
