@@ -1762,6 +1762,28 @@ __device__ void bitonic_desc(unsigned long long* key, uint32_t* val, int n) {
   }
 }
 
+// Sort of n unique keys, descending, by rank: key i goes to position =
+// the number of keys greater than it, found with n broadcast LDS reads per
+// key.  For the short lists of the selections (n <= kRankSortMax) this is
+// a few thousand cycles where the bitonic network's barrier stages take
+// several times more.  Positions >= keep are dropped; val (optional)
+// travels with its key; the destination must not overlap the source.
+constexpr int kRankSortMax = 512;
+__device__ void rank_sort_desc(const unsigned long long* key, const uint32_t* val, int n,
+                               unsigned long long* dkey, uint32_t* dval, int keep) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const unsigned long long ki = key[i];
+    int r = 0;
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) r += key[j] > ki ? 1 : 0;
+    if (r < keep) {
+      dkey[r] = ki;
+      if (val) dval[r] = val[i];
+    }
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ int pow2_at_least(int n) {
   int p = 1;
   while (p < n) p <<= 1;
@@ -1974,24 +1996,33 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     __syncthreads();
     m = min(s_n, (uint32_t)kSelCap);
   }
-  const int n2 = pow2_at_least((int)(m ? m : 1));
-  for (int i = (int)m + threadIdx.x; i < n2; i += blockDim.x) {
-    s_key[i] = 0ull;
-    s_slot[i] = 0xFFFFFFFFu;
-  }
-  __syncthreads();
-  bitonic_desc(s_key, s_slot, n2);
   const uint32_t out = min(kp, m);
+  unsigned long long* skey = s_key;
+  uint32_t* sslot = s_slot;
+  static_assert(kSelCap >= 2 * kRankSortMax, "rank sort destination");
+  if (m <= (uint32_t)kRankSortMax) {
+    skey = s_key + kRankSortMax;
+    sslot = s_slot + kRankSortMax;
+    rank_sort_desc(s_key, s_slot, (int)m, skey, sslot, (int)out);
+  } else {
+    const int n2 = pow2_at_least((int)m);
+    for (int i = (int)m + threadIdx.x; i < n2; i += blockDim.x) {
+      s_key[i] = 0ull;
+      s_slot[i] = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    bitonic_desc(s_key, s_slot, n2);
+  }
   for (uint32_t r = threadIdx.x; r < out; r += blockDim.x) {
-    a.sel_key[(uint64_t)q * a.rmax + r] = s_key[r];
-    a.sel_slot[(uint64_t)q * a.rmax + r] = s_slot[r];
+    a.sel_key[(uint64_t)q * a.rmax + r] = skey[r];
+    a.sel_slot[(uint64_t)q * a.rmax + r] = sslot[r];
   }
   if (threadIdx.x == 0) a.sel_cnt[q] = out;
   if (a.write_out) {
     const uint32_t kq = min(a.k[q], out);
     for (uint32_t r = threadIdx.x; r < a.k_max; r += blockDim.x) {
       const bool ok = r < kq;
-      const unsigned long long k = ok ? s_key[r] : 0ull;
+      const unsigned long long k = ok ? skey[r] : 0ull;
       a.out_ids[(uint64_t)q * a.k_max + r] = ok ? 0xFFFFFFFFu - (uint32_t)k : 0xFFFFFFFFu;
       a.out_scores[(uint64_t)q * a.k_max + r] = ok ? key2f((uint32_t)(k >> 32)) : -INFINITY;
     }
@@ -2152,10 +2183,16 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
     srt = s_sur;
     n = s_n;
   }
-  const int n2 = pow2_at_least((int)(n ? n : 1));
-  for (int i = (int)n + threadIdx.x; i < n2; i += blockDim.x) srt[i] = 0ull;
-  __syncthreads();
-  bitonic_desc(srt, nullptr, n2);
+  if (n <= (uint32_t)kRankSortMax) {
+    unsigned long long* dst = srt == s_key ? s_sur : s_key;   // the other buffer
+    rank_sort_desc(srt, nullptr, (int)n, dst, nullptr, (int)kq);
+    srt = dst;
+  } else {
+    const int n2 = pow2_at_least((int)n);
+    for (int i = (int)n + threadIdx.x; i < n2; i += blockDim.x) srt[i] = 0ull;
+    __syncthreads();
+    bitonic_desc(srt, nullptr, n2);
+  }
   for (uint32_t r = threadIdx.x; r < a.k_max; r += blockDim.x) {
     const bool ok = r < kq;
     const unsigned long long k = ok ? srt[r] : 0ull;
