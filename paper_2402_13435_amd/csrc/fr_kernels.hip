@@ -787,23 +787,21 @@ __global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
 #pragma unroll
   for (int j = 0; j < CH; ++j) bq[0][j] = qv ? qp[j * 64] : make_uint4(0, 0, 0, 0);
   const float qs = DT == kFP8 && qv ? a.qscale[q] : 1.f;
-  for (uint32_t t = t0; t < min(t0 + kSeedTilesPerWave, n_t); ++t) {
-    f32x16 acc[1];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[0][v] = 0.f;
-    mma_tile<DT, CH, 1>(acc, a.tiles + (uint64_t)t * (CH * 1024), bq, lane);
-    if (!qv) continue;
-    // predicate bits of the tile's 32 documents for this query (tile t is
-    // tile t % 32 of group t / 32: half of mask word (t % 32) / 2)
-    const uint32_t g = t / (uint32_t)(kGroup / kTile), tg = t % (uint32_t)(kGroup / kTile);
-    const uint64_t mword = a.mw[((uint64_t)g * kWords + (tg >> 1)) * a.ppad + pos];
+  // the two best keys among this lane's matching rows of tile t (0: none),
+  // from its products, the query's mask word of the tile (tile t is tile
+  // t % 32 of group t / 32: half of mask word (t % 32) / 2) and, for FP8,
+  // the lane's row scales (rows 8g + 4 half .. + 3 in xs[g])
+  auto keep_two = [&](uint32_t t, const f32x16& acc, uint64_t mword, const float4 (&xs)[4]) {
+    const uint32_t tg = t % (uint32_t)(kGroup / kTile);
     const uint32_t mrow = (uint32_t)(mword >> ((tg & 1u) * 32u)) >> (4 * half);
-    // the two best keys among this lane's matching rows (0: none)
     uint32_t k1 = 0u, k2 = 0u;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      float sc = acc[0][v];
-      if constexpr (DT == kFP8) sc = (sc * qs) * a.xscale[(uint64_t)t * kTile + acc_row(v, half)];
+      float sc = acc[v];
+      if constexpr (DT == kFP8) {
+        const float4 x4 = xs[v >> 2];
+        sc = (sc * qs) * ((v & 3) == 0 ? x4.x : (v & 3) == 1 ? x4.y : (v & 3) == 2 ? x4.z : x4.w);
+      }
       const uint32_t key = ((mrow >> (8 * (v >> 2) + (v & 3))) & 1u) ? fkey(sc) : 0u;
       const uint32_t lo = min(k1, key);
       k1 = max(k1, key);
@@ -811,6 +809,52 @@ __global__ __launch_bounds__(256) void k_seed_scores(SeedArgs a) {
     }
     *(uint2*)(a.skey + (uint64_t)pos * a.row + (uint64_t)t * 4u + 2u * (uint32_t)half) =
         make_uint2(k1, k2);
+  };
+  auto mask_word = [&](uint32_t t) -> uint64_t {
+    return a.mw[((uint64_t)(t / (uint32_t)(kGroup / kTile)) * kWords +
+                 (t % (uint32_t)(kGroup / kTile)) / 2u) * a.ppad + pos];
+  };
+  if constexpr (DT == kF32) {
+    const float4 none[4] = {};
+    for (uint32_t t = t0; t < min(t0 + kSeedTilesPerWave, n_t); ++t) {
+      f32x16 acc[1];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[0][v] = 0.f;
+      mma_tile<DT, CH, 1>(acc, a.tiles + (uint64_t)t * (CH * 1024), bq, lane);
+      if (qv) keep_two(t, acc[0], mask_word(t), none);
+    }
+  } else {
+    // BF16/FP8: every tile's A operand, mask word and row scales are loaded
+    // at once, with the query operand (one round of memory latency), then
+    // the tiles are scored with the scan's instruction sequence
+    constexpr int TPW = (int)kSeedTilesPerWave;
+    uint4 av[TPW][CH];
+    uint64_t mwd[TPW];
+    float4 xs[TPW][4];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const uint32_t t = t0 + (uint32_t)i;
+      const uint32_t tl = t < n_t ? t : t0;                 // an existing tile
+      const uint4* p = (const uint4*)(a.tiles + (uint64_t)tl * (CH * 1024)) + lane;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) av[i][j] = p[j * 64];
+      mwd[i] = (qv && t < n_t) ? mask_word(t) : 0ull;
+      if constexpr (DT == kFP8) {
+        const float4* s = (const float4*)(a.xscale + (uint64_t)tl * kTile) + half;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) xs[i][g] = s[2 * g];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const uint32_t t = t0 + (uint32_t)i;
+      if (t >= n_t) break;
+      f32x16 acc[1];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[0][v] = 0.f;
+      mma_chunks<DT, CH, 1, CH>(acc, av[i], 0, bq);
+      if (qv) keep_two(t, acc[0], mwd[i], xs[i]);
+    }
   }
 }
 
