@@ -599,6 +599,71 @@ def bench_sparse(args, torch):
     return 0
 
 
+def bench_streams(args, torch):
+    """Batches in flight on several streams, on the FP32 workload (1M x 128,
+    256 queries, K=100): QPS of back-to-back searches issued round robin on
+    1, 2 or 3 streams of one index with 2 or 3 workspaces, FP32 and the
+    BF16 (R=100) and FP8 (R=128) forms, tiling from the shipped table.  Each
+    point pre-warms for --prewarm-s, then takes the median of 5 runs of 40
+    searches; every stream's last results must equal the first stream's."""
+    import datagen
+    from paper_2402_13435_amd import Index, SearchResult
+    c, qb = datagen.workload("fp32")
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(qb.emb).to(dev)
+    table = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2402_13435_amd",
+                         "tuning", "gfx950.jsonl")
+
+    def outs():
+        return SearchResult(torch.empty((qb.n, 100), dtype=torch.int32, device=dev),
+                            torch.empty((qb.n, 100), dtype=torch.float32, device=dev),
+                            torch.empty(qb.n, dtype=torch.int32, device=dev),
+                            torch.empty(qb.n, dtype=torch.int64, device=dev))
+    points = []
+    for dt, r in (("f32", 0), ("bf16", 100), ("fp8", 128)):
+        for nws in (2, 3):
+            ix = Index(c.n, c.cfg.dim, c.cfg.vocab, 100, dtype=dt, rescore_r=r, max_batch=256,
+                       n_workspaces=nws)
+            ix.load_corpus(c.emb, c.ids, c.term_off, c.terms)
+            ix.tuning_load(table)
+            for ns in range(1, nws + 1):
+                ss = [torch.cuda.Stream() for _ in range(ns)]
+                oo = [outs() for _ in range(ns)]
+                i = 0
+                t_end = time.perf_counter() + args.prewarm_s
+                while i < 8 or time.perf_counter() < t_end:
+                    for _ in range(8):
+                        ix.search(q, qb, 100, out=oo[i % ns], stream=ss[i % ns])
+                        i += 1
+                    torch.cuda.synchronize()
+                runs = []
+                for _ in range(5):
+                    t0 = time.perf_counter()
+                    for j in range(40):
+                        ix.search(q, qb, 100, out=oo[j % ns], stream=ss[j % ns])
+                    torch.cuda.synchronize()
+                    runs.append(time.perf_counter() - t0)
+                el = sorted(runs)[2]
+                same = all(torch.equal(o.ids, oo[0].ids) and torch.equal(o.scores, oo[0].scores)
+                           for o in oo[1:])
+                points.append({"dtype": dt, "workspaces": nws, "streams": ns,
+                               "ms_per_search": round(el / 40 * 1e3, 4),
+                               "qps": round(qb.n * 40 / el, 1), "results_equal": same})
+                log(json.dumps(points[-1]))
+                if not same:
+                    ix.close()
+                    print(json.dumps({"error": "streams disagree", "point": points[-1]}))
+                    return 1
+            ix.close()
+    line = {"metric": "QPS with batches in flight on several streams",
+            "config": {"workload": f"streams: {c.n:,} docs x {c.cfg.dim}-d, vocab {c.cfg.vocab}, "
+                                   f"{qb.n} CNF queries at 0.1%-50% selectivity, K=100; BF16 R=100, "
+                                   "FP8 R=128", "n_docs": c.n},
+            "prewarm_s": args.prewarm_s, "points": points, "data": "synthetic"}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_serving(args, torch):
     line = serving_leg(args, torch, args.levels, args.level_s, args.n_docs)
     print(json.dumps(line), flush=True)
@@ -724,7 +789,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--config", default="fp32",
                     choices=["fp32", "precision", "batching", "serving", "qsweep", "quantk",
-                             "sparse"],
+                             "sparse", "streams"],
                     help="workload (default fp32: the benchmark line)")
     ap.add_argument("--n-docs", type=int, default=0, help="resize the corpus (non-default configs)")
     ap.add_argument("--q-sizes", default="1,8,32,64,128,256,512,1024",
@@ -771,6 +836,8 @@ def main() -> int:
         return bench_quantk(args, torch)
     if args.config == "sparse":
         return bench_sparse(args, torch)
+    if args.config == "streams":
+        return bench_streams(args, torch)
     t_start = time.perf_counter()
     log("generating the fp32 workload (1M docs x 128, 256 queries + a tuning batch)")
     c, qb = datagen.workload("fp32")
