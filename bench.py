@@ -815,7 +815,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the retrieval path runs on a single MI355X "
-              "(multi-GPU document sharding is a design note, not part of this build).",
+              "(sharding the documents over several GPUs is not implemented).",
               file=sys.stderr)
         return 2
     import torch

@@ -44,7 +44,7 @@ typedef enum {
   FR_ECAPACITY = -3,     /* more live documents than `capacity` */
   FR_EDUPID = -4,        /* inserting an id that is already live */
   FR_ENOTFOUND = -5,     /* deleting an id that is not live */
-  FR_EUNSUPPORTED = -6,  /* configuration or input this build does not handle */
+  FR_EUNSUPPORTED = -6,  /* configuration or input this library does not handle */
   FR_EDEVICE = -7,       /* a HIP call failed; the index is no longer usable */
   FR_EBUSY = -8          /* no free workspace and FR_NOWAIT was given */
 } fr_status;
@@ -412,7 +412,7 @@ fr_status fr_debug_candidates(fr_index* ix, uint32_t n_q, uint32_t* out_ids,
  * `groups_per_item` groups per work item, used when a batch has more than
  * 32 query tiles (below that the scan cuts the corpus into equal tile
  * ranges, one item per workgroup).  Zeros restore the per-batch
- * defaults.  FR_EUNSUPPORTED if this build has no such scan kernel for the
+ * defaults.  FR_EUNSUPPORTED if this library has no such scan kernel for the
  * index's dtype and dimension.  Used by the autotuner and by tests. */
 fr_status fr_set_tiling(fr_index* ix, uint32_t query_blocks, uint32_t waves,
                         uint32_t groups_per_item);
@@ -451,7 +451,7 @@ fr_status fr_set_strategy(fr_index* ix, uint32_t strategy, int pinned);
  * size trades latency for throughput; here the tile shape, the items and the
  * selection strategy are tuned per batch shape).  On the given batch (host
  * pointers; a trial is one unmeasured search and the median device time of
- * the next ones; outputs are scratch) it times every scan tiling this build
+ * the next ones; outputs are scratch) it times every scan tiling this library
  * has for the index's dtype and dimension with the default strategy, then
  * the other strategies with the three fastest tilings (3 searches per
  * trial), and the three fastest trials again (9 searches each).  The winner is recorded
@@ -484,7 +484,7 @@ fr_status fr_debug_codes(fr_index* ix, uint64_t slot0, uint64_t n, uint64_t* out
 fr_status fr_tuning_save(fr_index* ix, const char* path);
 
 /* Add the entries of a file written by fr_tuning_save that match this
- * index (same arch, dtype, dim and vocab, and a tiling this build has) to its
+ * index (same arch, dtype, dim and vocab, and a tiling this library has) to its
  * tuning table; other lines are skipped.  `out_loaded` (may be NULL)
  * receives how many were added. */
 fr_status fr_tuning_load(fr_index* ix, const char* path, uint32_t* out_loaded);

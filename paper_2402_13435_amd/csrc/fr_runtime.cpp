@@ -2379,9 +2379,9 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
     uint32_t strat;
     float ms;
   };
-  // Round 1: every tiling with the default strategy, then the other
+  // Stage 1: every tiling with the default strategy, then the other
   // strategies with the three fastest tilings, 3 timed searches each.
-  // Round 2: the three fastest trials again with 9 timed searches each
+  // Stage 2: the three fastest trials again with 9 timed searches each
   // (near-equal candidates are told apart by the longer median).
   std::vector<Trial> trials;
   for (int nw : {4, 8}) {
@@ -2426,7 +2426,7 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
     }
   }
   std::sort(trials.begin(), trials.end(), by_ms);
-  // Round 3: sparse routing levels on the winner (3 searches each), the
+  // Stage 3: sparse routing levels on the winner (3 searches each), the
   // fastest level again with 9 against the winner without routing.
   {
     Trial base = trials[0], lv_best = base;
