@@ -450,8 +450,10 @@ fr_status fr_set_strategy(fr_index* ix, uint32_t strategy, int pinned);
 /* The autotuner of the batch form (appendix, "Batch Inference": the batch
  * size trades latency for throughput; here the tile shape, the items and the
  * selection strategy are tuned per batch shape).  On the given batch (host
- * pointers; a trial is one unmeasured search and the median device time of
- * the next ones; outputs are scratch) it times every scan tiling this library
+ * pointers; outputs are scratch) it first searches untimed for half a second
+ * (the GPU's clocks settle to their sustained level), then, a trial being
+ * one unmeasured search and the median device time of the next ones, it
+ * times every scan tiling this library
  * has for the index's dtype and dimension with the default strategy, then
  * the other strategies with the three fastest tilings (3 searches per
  * trial), and the three fastest trials again (9 searches each).  The winner is recorded

@@ -18,6 +18,7 @@ constexpr int kSelCap = 8192;        // candidates sorted in LDS by the select k
 constexpr int kMaxR = 4096;          // largest K / R handled by select and rescore
 // corpus groups sampled for starting thresholds: FP32 scores cost 16x the
 // matrix time of BF16 ones, so the quantised forms sample more
+constexpr int kTunePrewarmMs = 500;     // untimed searches before the autotuner's trials
 constexpr int kSeedGroupsF32 = 32;
 constexpr int kSeedGroupsLow = 64;
 constexpr int kSeedGroupsMax = 128;

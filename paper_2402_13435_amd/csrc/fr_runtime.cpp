@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <cstdio>
@@ -2379,6 +2380,20 @@ fr_status fr_autotune(fr_index* ix, uint32_t n_q, const float* queries, const fr
     uint32_t strat;
     float ms;
   };
+  // Untimed searches for kTunePrewarmMs first: in the first tenths of a
+  // second of searching after an idle spell the GPU clocks higher than it
+  // settles to under sustained load, which would favour the trials that
+  // happen to run first.
+  {
+    const auto t_end = std::chrono::steady_clock::now() + std::chrono::milliseconds(kTunePrewarmMs);
+    int n = 0;
+    while (n < 2 || std::chrono::steady_clock::now() < t_end) {
+      fr_status st = fr_search(ix, n_q, queries, cnf, k, ids.data(), sc.data(), cnt.data(),
+                               nm.data(), nullptr, 0);
+      if (st != FR_OK) return st;
+      ++n;
+    }
+  }
   // Stage 1: every tiling with the default strategy, then the other
   // strategies with the three fastest tilings, 3 timed searches each.
   // Stage 2: the three fastest trials again with 9 timed searches each
